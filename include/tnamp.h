@@ -1,0 +1,192 @@
+/*
+ * tnamp.h - C ABI of the MI355X tensor-network amplitude engine.
+ *
+ * The library executes contraction plans for circuit amplitudes
+ * a(x) = <x|C|0^n>.  A plan is the paper's separator-hierarchy contraction
+ * order (proof of Theorem 1; Algorithm 1 and the supplemental section on the
+ * numerical implementation) over the circuit's tensor network (section on
+ * classical simulation of quantum circuits: gates as tensors, the initial
+ * |0> and the projection onto |x> absorbed into them), with index slicing.
+ * Every pairwise step of the plan multiplies entries over the union of both
+ * operands' indices and sums the shared indices (Eq. (3)); on the device it
+ * runs as an index permutation followed by a batched complex GEMM.
+ *
+ * Conventions
+ *  - Bitstrings are uint64 words; bit q is the output value x_q of qubit q
+ *    (plans have at most 64 qubits).
+ *  - Results are complex128, written as 2*nb doubles: re, im per bitstring,
+ *    in the order of the input words.
+ *  - Slices are summed in float64 in ascending slice order; within a slice
+ *    the arithmetic is float32 (complex64 storage), or split 16-bit products
+ *    with float32 accumulation, as selected by `precision`.  The reduction
+ *    order of every step is fixed by the plan, so a result does not depend on
+ *    batch size, chunking or other work on the device.
+ *  - All calls return TN_OK (0), TN_PENDING (1) or a negative error code;
+ *    tn_last_error() gives a thread-local message for the last error.
+ *  - Host pointers are owned by the caller and only read (or, for outputs,
+ *    written) during the call.  Device memory, plans and streams created by
+ *    the library are owned by the library.
+ */
+#ifndef TNAMP_H
+#define TNAMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TN_OK 0
+#define TN_PENDING 1
+#define TN_EINVAL (-1)      /* bad argument or malformed plan blob          */
+#define TN_ENOMEM (-2)      /* request can never fit in the arena            */
+#define TN_EBUSY (-3)       /* plan still referenced by pending requests     */
+#define TN_EDEVICE (-4)     /* HIP error; the context is poisoned            */
+#define TN_ECANCELLED (-5)  /* request was cancelled                         */
+#define TN_ENOTFOUND (-6)   /* unknown ticket                                */
+
+/* precision modes */
+#define TN_FP32_4M 0        /* complex64 operands, 4 real products, FP32 MFMA   */
+#define TN_FP32_3M 1        /* complex64 operands, 3 real products (Gauss)      */
+#define TN_SPLIT_BF16 2     /* x = hi + lo in bf16, hi*hi + hi*lo + lo*hi, FP32 acc */
+#define TN_SPLIT_FP16 3     /* same with fp16 halves and power-of-two scaling   */
+
+typedef struct tn_ctx tn_ctx;
+typedef struct tn_plan tn_plan;
+
+typedef struct tn_plan_info_t {
+    int32_t n_qubits;
+    int32_t n_leaves;
+    int32_t n_steps;
+    int32_t n_sliced;                 /* log2 of the number of slices            */
+    int32_t max_rank;                 /* widest intermediate, labels (batch excl.) */
+    int32_t reserved;
+    double flops_per_slice_per_b;     /* algorithmic real flops, 8 per complex MAC */
+    double flops_total_per_b;         /* over all slices, with slice reuse       */
+    uint64_t peak_bytes_fixed;        /* workspace independent of the batch size */
+    uint64_t peak_bytes_per_b;        /* plus this much per bitstring in a chunk */
+} tn_plan_info_t;
+
+typedef struct tn_req_stats {
+    int64_t t_arrive_ns;              /* tn_submit                      */
+    int64_t t_admit_ns;               /* memory granted                 */
+    int64_t t_start_ns;               /* first kernel enqueued          */
+    int64_t t_end_ns;                 /* results on the host            */
+    int32_t batch;                    /* bitstrings in the device batch */
+    int32_t plan_id;
+} tn_req_stats;
+
+/*
+ * tn_ctx_create: one context per device.
+ *   device     HIP device ordinal.
+ *   arena      device pointer to caller-owned memory (e.g. a torch uint8
+ *              tensor) or NULL to let the library allocate `arena_bytes`.
+ *   arena_bytes size of the arena; every plan's workspace comes from it.
+ * Errors: TN_EINVAL (bad device / size), TN_EDEVICE (allocation failed).
+ */
+int tn_ctx_create(int device, void* arena, size_t arena_bytes, tn_ctx** out);
+
+/* Tear down: waits for pending work, frees library allocations. */
+int tn_ctx_destroy(tn_ctx* ctx);
+
+/*
+ * tn_plan_load: copy and validate a TNP1 blob (written by the plan builder),
+ * convert leaves from complex128 to complex64 (round to nearest even) and
+ * upload them.  The plan stays resident until unloaded.
+ * Errors: TN_EINVAL (malformed blob: bad magic/version, truncated, label out
+ * of range, dimension other than 2, operand used twice, step orders that do
+ * not form a batched GEMM), TN_EDEVICE.
+ */
+int tn_plan_load(tn_ctx* ctx, const void* blob, size_t nbytes, tn_plan** out);
+
+/* Parse and validate a blob on the host only (no device needed). */
+int tn_plan_validate(const void* blob, size_t nbytes, tn_plan_info_t* info);
+
+int tn_plan_info(const tn_plan* plan, tn_plan_info_t* out);
+
+/* TN_EBUSY while requests on the plan are pending. */
+int tn_plan_unload(tn_ctx* ctx, tn_plan* plan);
+
+/*
+ * tn_contract_amplitudes: blocking.  bits[nb] -> out_re_im[2*nb].
+ *   precision   one of the TN_* precision modes.
+ *   hip_stream  a hipStream_t to run on, or NULL for the context's stream.
+ * The batch is processed in chunks sized to the arena.
+ * Errors: TN_EINVAL (nb <= 0, a bit set at position >= n_qubits, bad mode),
+ * TN_ENOMEM (one bitstring does not fit), TN_EDEVICE.
+ */
+int tn_contract_amplitudes(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits,
+                           int32_t nb, int32_t precision, void* hip_stream,
+                           double* out_re_im);
+
+/*
+ * tn_submit / tn_poll / tn_cancel: the serving loop.  tn_submit copies
+ * `bits` and returns at once with a ticket; a scheduler thread admits
+ * requests as arena memory and execution slots free up (admission by the
+ * plan's peak bytes at the request's batch), merges queued requests on the
+ * same plan and precision into one device batch, and runs admitted batches
+ * concurrently on separate streams.  tn_poll returns TN_PENDING until the
+ * request is done, then TN_OK with the amplitudes (and stats if st != NULL);
+ * a ticket can be polled to completion once.
+ * Errors: TN_ENOMEM at submit when one bitstring of the plan cannot fit the
+ * arena at all; TN_ECANCELLED from tn_poll after tn_cancel.
+ */
+int tn_submit(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int32_t nb,
+              int32_t precision, uint64_t* ticket);
+int tn_poll(tn_ctx* ctx, uint64_t ticket, double* out_re_im, tn_req_stats* st);
+int tn_cancel(tn_ctx* ctx, uint64_t ticket);
+
+/* Serving configuration: number of concurrent slots (streams), max merged
+ * batch.  Call before the first tn_submit. */
+int tn_server_config(tn_ctx* ctx, int32_t n_slots, int32_t max_batch);
+
+/* Stop the scheduler and slot threads (pending work finishes first);
+ * tn_ctx_destroy calls it. */
+int tn_server_stop(tn_ctx* ctx);
+
+/* Per-context counters of the last tn_contract_amplitudes call (debug):
+ * kernel time is not measured here; these are host-side counts. */
+typedef struct tn_exec_stats {
+    int64_t kernels_gemm;
+    int64_t kernels_permute;
+    int64_t kernels_gather;
+    int64_t steps_executed;
+    int64_t steps_reused;
+    int32_t chunk;                    /* bitstrings per device chunk */
+    int32_t n_chunks;
+    double algorithmic_flops;         /* sum over executed steps     */
+    double permute_bytes;             /* 16 bytes per permuted element */
+} tn_exec_stats;
+int tn_last_exec_stats(tn_ctx* ctx, tn_exec_stats* out);
+
+/*
+ * Kernel entry points on caller-owned device memory (complex64 interleaved),
+ * for kernel tests and per-kernel measurement.  They enqueue on `hip_stream`
+ * (NULL = the default stream) and do not synchronise.
+ *
+ * tn_kernel_cgemm: for ob < nb, ib < nbatch:
+ *   C[ob*sCb + ib*sCi + m*N + n] = sum_k A(m,k) * B(k,n)
+ *   A(m,k) = A[ob*sAb + ib*sAi + (transA ? k*M + m : m*K + k)]
+ *   B(k,n) = B[ob*sBb + ib*sBi + (transB ? n*K + k : k*N + n)]
+ *   strides in complex elements; sAb or sBb may be 0 (broadcast).
+ *   precision TN_FP32_4M or TN_SPLIT_BF16.  Returns TN_EINVAL for
+ *   non-positive sizes, TN_EDEVICE on a launch error.
+ * tn_kernel_permute: bit permutation of the element index:
+ *   dst[b*2^rank + sum_p bit_{perm[p]}(i) << p] = src[b*2^rank + i]
+ *   (destination bit p takes source bit perm[p]); rank <= 40, perm must be a
+ *   permutation of 0..rank-1 (TN_EINVAL otherwise).
+ */
+int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N, int32_t K,
+                    int32_t transA, int32_t transB, int32_t nbatch, int32_t nb,
+                    int64_t sAb, int64_t sBb, int64_t sCb, int64_t sAi, int64_t sBi,
+                    int64_t sCi, int32_t precision, void* hip_stream);
+int tn_kernel_permute(const void* src, void* dst, int32_t rank, const int32_t* perm,
+                      int32_t nb, void* hip_stream);
+
+const char* tn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNAMP_H */

@@ -1,0 +1,56 @@
+// Kernel argument blocks and launchers (device code in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define TN_MAX_GATHER 24
+#define TN_MAX_TILE 16
+#define TN_MAX_BITS 48
+
+struct GatherArgs {
+    const float2* src;
+    float2* dst;
+    const uint64_t* bits;     // bitstrings of the chunk (one per b)
+    uint32_t slice;
+    int nb;                   // batch count (chunk if the leaf has outputs, else 1)
+    int n_mat, n_out, n_sl;
+    int mat_src[TN_MAX_GATHER];
+    int out_src[TN_MAX_GATHER];
+    int out_qubit[TN_MAX_GATHER];
+    int sl_src[TN_MAX_GATHER];
+    int sl_bit[TN_MAX_GATHER];
+};
+
+struct PermArgs {
+    const float2* src;
+    float2* dst;
+    int rank;                 // bits per b
+    int nb;                   // batch count
+    int nt;                   // tile bits
+    int nn;                   // non-tile bits
+    int t_in[TN_MAX_TILE];    // tile bit m (input order) -> input bit position
+    int t_out[TN_MAX_TILE];   // tile bit m (output order) -> output bit position
+    int t_rank[TN_MAX_TILE];  // tile bit m (output order) -> its index in input order
+    int n_in[TN_MAX_BITS];    // non-tile bit m -> input bit position
+    int n_out[TN_MAX_BITS];   // non-tile bit m -> output bit position
+};
+
+struct GemmArgs {
+    const float2* A;
+    const float2* B;
+    float2* C;
+    int M, N, K;
+    int transA, transB;       // A stored [K][M] / B stored [N][K]
+    int nbatch;               // inner batch count (batch labels)
+    int nb;                   // outer batch count (bitstrings)
+    long long sAb, sBb, sCb;  // outer strides (elements); 0 = broadcast
+    long long sAi, sBi, sCi;  // inner strides
+};
+
+hipError_t launch_gather(const GatherArgs& g, hipStream_t s);
+hipError_t launch_permute(const PermArgs& a, hipStream_t s);
+hipError_t launch_gemm(const GemmArgs& g, int precision, hipStream_t s);
+int gemm_kind(const GemmArgs& g, int precision);
+hipError_t launch_zero_acc(double2* acc, int nb, hipStream_t s);
+hipError_t launch_accumulate(double2* acc, const float2* v, int nb, int v_has_b, hipStream_t s);
+hipError_t launch_finalize(double2* acc, int nb, double sre, double sim, hipStream_t s);

@@ -1,0 +1,419 @@
+// Context, plan residency and the executor of the amplitude engine.
+//
+// The executor walks the plan's pairwise steps for every slice of a chunk of
+// bitstrings: leaves are gathered (bitstring bits replace output labels,
+// slice bits replace sliced labels), operands that do not fit the step's
+// batched-GEMM form are permuted, the step's complex GEMM writes the result,
+// and after the last step the chunk's scalars are added in float64 to the
+// per-bitstring accumulators (slices in ascending order).  A step whose
+// subtree depends only on slice bits that did not change since the previous
+// slice keeps its previous result.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <limits>
+
+#include "kernels.h"
+#include "tn_internal.h"
+
+namespace tn {
+
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+#define HIPCHK(ctx, expr)                                                        \
+    do {                                                                         \
+        hipError_t e_ = (expr);                                                  \
+        if (e_ != hipSuccess) {                                                  \
+            set_error(std::string("HIP error: ") + hipGetErrorString(e_) +       \
+                      " at " #expr);                                             \
+            if (ctx) (ctx)->poisoned = true;                                     \
+            return TN_EDEVICE;                                                   \
+        }                                                                        \
+    } while (0)
+
+static void fill_perm(PermArgs& pa, const int* map, int r) {
+    int inv[kMaxRank];
+    for (int p = 0; p < r; ++p) inv[map[p]] = p;
+    const int target = std::min(r, 10);
+    std::vector<char> inT(r, 0);
+    int a = 0, c = 0, t = 0;
+    auto add = [&](int q) { if (!inT[q]) { inT[q] = 1; ++t; } };
+    while (t < target) {
+        if (a <= c && a < r) add(a++);
+        else if (c < r) add(map[c++]);
+        else if (a < r) add(a++);
+        else break;
+    }
+    pa.rank = r;
+    pa.nt = t;
+    int m = 0;
+    for (int q = 0; q < r; ++q)
+        if (inT[q]) pa.t_in[m++] = q;
+    m = 0;
+    for (int p = 0; p < r; ++p)
+        if (inT[map[p]]) {
+            pa.t_out[m] = p;
+            int rk = 0;
+            while (pa.t_in[rk] != map[p]) ++rk;
+            pa.t_rank[m] = rk;
+            ++m;
+        }
+    m = 0;
+    for (int q = 0; q < r; ++q)
+        if (!inT[q]) {
+            pa.n_in[m] = q;
+            pa.n_out[m] = inv[q];
+            ++m;
+        }
+    pa.nn = m;
+}
+
+static int choose_chunk(const tn_plan* plan, int nb, size_t ws_bytes) {
+    tn_plan* pl = const_cast<tn_plan*>(plan);
+    if (pl->mem(1).bytes > ws_bytes) return 0;
+    int lo = 1, hi = nb;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (pl->mem(mid).bytes <= ws_bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int precision,
+            hipStream_t stream, char* ws, size_t ws_bytes, double* out, tn_exec_stats* stats) {
+    const PlanHost& p = plan->host;
+    tn_plan* pl = const_cast<tn_plan*>(plan);
+    tn_exec_stats es{};
+    const int chunk = choose_chunk(plan, nb, ws_bytes);
+    if (chunk <= 0) {
+        set_error("one bitstring of this plan needs more workspace than available");
+        return TN_ENOMEM;
+    }
+    const MemPlan& mp = pl->mem(chunk);
+    const int S = (int)p.sliced.size();
+    const uint64_t nslices = 1ull << S;
+    const int nL = (int)p.leaves.size();
+    std::vector<double> host_acc;
+    es.chunk = chunk;
+    for (int c0 = 0; c0 < nb; c0 += chunk) {
+        const int cb = std::min(chunk, nb - c0);
+        es.n_chunks++;
+        uint64_t* d_bits = reinterpret_cast<uint64_t*>(ws + mp.bits_off);
+        double2* d_acc = reinterpret_cast<double2*>(ws + mp.acc_off);
+        HIPCHK(ctx, hipMemcpyAsync(d_bits, bits + c0, sizeof(uint64_t) * cb, hipMemcpyHostToDevice, stream));
+        HIPCHK(ctx, launch_zero_acc(d_acc, cb, stream));
+        auto tensor_ptr = [&](int t) -> float2* {
+            if (t < nL && p.leaves[t].identity)
+                return reinterpret_cast<float2*>(plan->d_leaves) + p.leaves[t].dev_off;
+            return reinterpret_cast<float2*>(ws + mp.tensor_off[t]);
+        };
+        for (uint64_t s = 0; s < nslices; ++s) {
+            const uint32_t changed = s == 0 ? 0xffffffffu : (uint32_t)(s ^ (s - 1));
+            auto gather = [&](int t) -> int {
+                if (t >= nL) return TN_OK;
+                const Leaf& lf = p.leaves[t];
+                if (lf.identity) return TN_OK;
+                if (!(s == 0 || (lf.slice_mask & changed))) return TN_OK;
+                GatherArgs g{};
+                g.src = reinterpret_cast<const float2*>(plan->d_leaves) + lf.dev_off;
+                g.dst = tensor_ptr(t);
+                g.bits = d_bits;
+                g.slice = (uint32_t)s;
+                g.nb = lf.has_b ? cb : 1;
+                g.n_mat = lf.n_mat;
+                g.n_out = lf.n_out;
+                g.n_sl = lf.n_sl;
+                for (int i = 0; i < lf.n_mat; ++i) g.mat_src[i] = lf.mat_src[i];
+                for (int i = 0; i < lf.n_out; ++i) { g.out_src[i] = lf.out_src[i]; g.out_qubit[i] = lf.out_qubit[i]; }
+                for (int i = 0; i < lf.n_sl; ++i) { g.sl_src[i] = lf.sl_src[i]; g.sl_bit[i] = lf.sl_bit[i]; }
+                HIPCHK(ctx, launch_gather(g, stream));
+                es.kernels_gather++;
+                return TN_OK;
+            };
+            if (p.steps.empty()) {
+                int rc = gather(0);
+                if (rc) return rc;
+            }
+            for (size_t si = 0; si < p.steps.size(); ++si) {
+                const Step& st = p.steps[si];
+                if (!(s == 0 || (st.dep_mask & changed))) {
+                    es.steps_reused++;
+                    continue;
+                }
+                int rc = gather(st.a);
+                if (rc) return rc;
+                rc = gather(st.b);
+                if (rc) return rc;
+                const float2* pa = tensor_ptr(st.a);
+                const float2* pb = tensor_ptr(st.b);
+                if (st.permA) {
+                    PermArgs a{};
+                    fill_perm(a, st.permA_map, (int)st.orderA.size());
+                    a.src = pa;
+                    a.dst = reinterpret_cast<float2*>(ws + mp.permA_off[si]);
+                    a.nb = st.hbA ? cb : 1;
+                    HIPCHK(ctx, launch_permute(a, stream));
+                    es.kernels_permute++;
+                    es.permute_bytes += 16.0 * std::ldexp(1.0, a.rank) * a.nb;
+                    pa = a.dst;
+                }
+                if (st.permB) {
+                    PermArgs a{};
+                    fill_perm(a, st.permB_map, (int)st.orderB.size());
+                    a.src = pb;
+                    a.dst = reinterpret_cast<float2*>(ws + mp.permB_off[si]);
+                    a.nb = st.hbB ? cb : 1;
+                    HIPCHK(ctx, launch_permute(a, stream));
+                    es.kernels_permute++;
+                    es.permute_bytes += 16.0 * std::ldexp(1.0, a.rank) * a.nb;
+                    pb = a.dst;
+                }
+                const long long nbat = 1ll << st.batch_bits;
+                const long long M = 1ll << st.m_bits, N = 1ll << st.n_bits, K = 1ll << st.k_bits;
+                GemmArgs g{};
+                const int nbC = st.hbC ? cb : 1;
+                float2* pc = tensor_ptr(st.c);
+                if (!st.swapC) {
+                    g.A = pa; g.B = pb; g.C = pc;
+                    g.M = (int)M; g.N = (int)N; g.K = (int)K;
+                    g.transA = st.transA; g.transB = st.transB;
+                    g.sAb = st.hbA ? nbat * M * K : 0; g.sAi = M * K;
+                    g.sBb = st.hbB ? nbat * K * N : 0; g.sBi = K * N;
+                } else {
+                    // C^T = B^T A^T
+                    g.A = pb; g.B = pa; g.C = pc;
+                    g.M = (int)N; g.N = (int)M; g.K = (int)K;
+                    g.transA = !st.transB; g.transB = !st.transA;
+                    g.sAb = st.hbB ? nbat * K * N : 0; g.sAi = K * N;
+                    g.sBb = st.hbA ? nbat * M * K : 0; g.sBi = M * K;
+                }
+                g.sCb = nbat * M * N; g.sCi = M * N;
+                g.nbatch = (int)nbat;
+                g.nb = nbC;
+                HIPCHK(ctx, launch_gemm(g, precision, stream));
+                es.kernels_gemm++;
+                es.steps_executed++;
+                es.algorithmic_flops += st.flops_per_b * nbC;
+            }
+            const int root = p.root;
+            HIPCHK(ctx, launch_accumulate(d_acc, tensor_ptr(root), cb, p.has_b[root], stream));
+        }
+        HIPCHK(ctx, launch_finalize(d_acc, cb, p.scale.real(), p.scale.imag(), stream));
+        HIPCHK(ctx, hipMemcpyAsync(out + 2 * (size_t)c0, d_acc, sizeof(double2) * cb, hipMemcpyDeviceToHost, stream));
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+    }
+    if (stats) *stats = es;
+    return TN_OK;
+}
+
+}  // namespace tn
+
+using namespace tn;
+
+extern "C" {
+
+const char* tn_last_error(void) { return g_err.c_str(); }
+
+int tn_ctx_create(int device, void* arena, size_t arena_bytes, tn_ctx** out) {
+    if (!out) { set_error("null out"); return TN_EINVAL; }
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        set_error("no such HIP device");
+        return TN_EINVAL;
+    }
+    if (arena_bytes < (1u << 20)) { set_error("arena too small (< 1 MiB)"); return TN_EINVAL; }
+    std::unique_ptr<tn_ctx> c(new tn_ctx());
+    c->device = device;
+    HIPCHK((tn_ctx*)nullptr, hipSetDevice(device));
+    HIPCHK((tn_ctx*)nullptr, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    if (arena) {
+        c->arena = static_cast<char*>(arena);
+        c->own_arena = false;
+    } else {
+        void* ptr = nullptr;
+        hipError_t e = hipMalloc(&ptr, arena_bytes);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(c->stream);
+            set_error(std::string("arena allocation failed: ") + hipGetErrorString(e));
+            return TN_EDEVICE;
+        }
+        c->arena = static_cast<char*>(ptr);
+        c->own_arena = true;
+    }
+    c->arena_bytes = arena_bytes;
+    c->free_list[0] = arena_bytes;
+    *out = c.release();
+    return TN_OK;
+}
+
+int tn_server_stop(tn_ctx* ctx);
+
+int tn_ctx_destroy(tn_ctx* ctx) {
+    if (!ctx) return TN_EINVAL;
+    tn_server_stop(ctx);
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamDestroy(ctx->stream);
+    if (ctx->own_arena) (void)hipFree(ctx->arena);
+    delete ctx;
+    return TN_OK;
+}
+
+int tn_plan_validate(const void* blob, size_t nbytes, tn_plan_info_t* info) {
+    PlanHost p;
+    int rc = parse_plan(blob, nbytes, p);
+    if (rc) return rc;
+    if (info) {
+        tn_plan tmp;
+        tmp.host = std::move(p);
+        return tn_plan_info(&tmp, info);
+    }
+    return TN_OK;
+}
+
+int tn_plan_info(const tn_plan* plan, tn_plan_info_t* out) {
+    if (!plan || !out) { set_error("null argument"); return TN_EINVAL; }
+    const PlanHost& p = plan->host;
+    tn_plan* pl = const_cast<tn_plan*>(plan);
+    out->n_qubits = p.n_qubits;
+    out->n_leaves = (int)p.leaves.size();
+    out->n_steps = (int)p.steps.size();
+    out->n_sliced = (int)p.sliced.size();
+    out->max_rank = p.max_rank;
+    out->reserved = 0;
+    out->flops_per_slice_per_b = p.flops_per_slice_per_b;
+    out->flops_total_per_b = p.flops_total_per_b;
+    size_t m1 = pl->mem(1).bytes, m2 = pl->mem(2).bytes;
+    out->peak_bytes_per_b = m2 > m1 ? m2 - m1 : 0;
+    out->peak_bytes_fixed = m1 > out->peak_bytes_per_b ? m1 - out->peak_bytes_per_b : 0;
+    return TN_OK;
+}
+
+int tn_plan_load(tn_ctx* ctx, const void* blob, size_t nbytes, tn_plan** out) {
+    if (!ctx || !out) { set_error("null argument"); return TN_EINVAL; }
+    if (ctx->poisoned) { set_error("context poisoned by an earlier device error"); return TN_EDEVICE; }
+    *out = nullptr;
+    std::unique_ptr<tn_plan> pl(new tn_plan());
+    int rc = parse_plan(blob, nbytes, pl->host);
+    if (rc) return rc;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const size_t elems = pl->host.leaf_pool_elems;
+    HIPCHK(ctx, hipMalloc(&pl->d_leaves, std::max<size_t>(elems, 1) * 8));
+    std::vector<float> staging(2 * elems);
+    for (auto& lf : pl->host.leaves) {
+        std::copy(lf.data.begin(), lf.data.end(), staging.begin() + 2 * lf.dev_off);
+    }
+    HIPCHK(ctx, hipMemcpy(pl->d_leaves, staging.data(), staging.size() * sizeof(float), hipMemcpyHostToDevice));
+    pl->id = ctx->next_plan_id++;
+    *out = pl.release();
+    return TN_OK;
+}
+
+int tn_plan_unload(tn_ctx* ctx, tn_plan* plan) {
+    if (!ctx || !plan) { set_error("null argument"); return TN_EINVAL; }
+    if (plan->pending.load() > 0) { set_error("plan has pending requests"); return TN_EBUSY; }
+    (void)hipSetDevice(ctx->device);
+    (void)hipFree(plan->d_leaves);
+    delete plan;
+    return TN_OK;
+}
+
+int tn_contract_amplitudes(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int32_t nb,
+                           int32_t precision, void* hip_stream, double* out_re_im) {
+    if (!ctx || !plan || !bits || !out_re_im) { set_error("null argument"); return TN_EINVAL; }
+    if (nb <= 0) { set_error("nb must be positive"); return TN_EINVAL; }
+    if (precision != TN_FP32_4M && precision != TN_SPLIT_BF16) {
+        set_error("precision mode not available");
+        return TN_EINVAL;
+    }
+    if (ctx->poisoned) { set_error("context poisoned by an earlier device error"); return TN_EDEVICE; }
+    const uint64_t allowed = plan->host.out_mask;
+    for (int i = 0; i < nb; ++i)
+        if (bits[i] & ~allowed) { set_error("bitstring has a bit at a position >= n_qubits"); return TN_EINVAL; }
+    std::lock_guard<std::mutex> g(ctx->mu);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->stream;
+    // workspace: the largest free region of the arena (all of it when the
+    // serving loop is idle); wait for served batches to release memory when
+    // not even one bitstring fits
+    const size_t need1 = const_cast<tn_plan*>(plan)->mem(1).bytes;
+    if (need1 > ctx->arena_bytes) {
+        set_error("one bitstring of this plan needs more workspace than the arena holds");
+        return TN_ENOMEM;
+    }
+    size_t off = 0, bytes = 0;
+    {
+        std::unique_lock<std::mutex> lk(ctx->smu);
+        ctx->scv.wait(lk, [&] { return largest_free(ctx) >= need1; });
+        bytes = largest_free(ctx);
+        arena_alloc(ctx, bytes, &off);
+    }
+    tn_exec_stats st{};
+    int rc = execute(ctx, plan, bits, nb, precision, s, ctx->arena + off, bytes, out_re_im, &st);
+    {
+        std::lock_guard<std::mutex> lk(ctx->smu);
+        arena_free(ctx, off, bytes);
+        ctx->scv.notify_all();
+    }
+    ctx->last = st;
+    return rc;
+}
+
+int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N, int32_t K,
+                    int32_t transA, int32_t transB, int32_t nbatch, int32_t nb,
+                    int64_t sAb, int64_t sBb, int64_t sCb, int64_t sAi, int64_t sBi,
+                    int64_t sCi, int32_t precision, void* hip_stream) {
+    if (!A || !B || !C || M <= 0 || N <= 0 || K <= 0 || nbatch <= 0 || nb <= 0) {
+        set_error("bad gemm arguments");
+        return TN_EINVAL;
+    }
+    if (precision != TN_FP32_4M && precision != TN_SPLIT_BF16) { set_error("precision mode not available"); return TN_EINVAL; }
+    GemmArgs g{};
+    g.A = static_cast<const float2*>(A);
+    g.B = static_cast<const float2*>(B);
+    g.C = static_cast<float2*>(C);
+    g.M = M; g.N = N; g.K = K;
+    g.transA = transA ? 1 : 0; g.transB = transB ? 1 : 0;
+    g.nbatch = nbatch; g.nb = nb;
+    g.sAb = sAb; g.sBb = sBb; g.sCb = sCb; g.sAi = sAi; g.sBi = sBi; g.sCi = sCi;
+    tn_ctx* none = nullptr;
+    HIPCHK(none, launch_gemm(g, precision, static_cast<hipStream_t>(hip_stream)));
+    return TN_OK;
+}
+
+int tn_kernel_permute(const void* src, void* dst, int32_t rank, const int32_t* perm, int32_t nb,
+                      void* hip_stream) {
+    if (!src || !dst || !perm || rank < 0 || rank > 40 || nb <= 0) { set_error("bad permute arguments"); return TN_EINVAL; }
+    int map[kMaxRank];
+    std::vector<char> seen(rank, 0);
+    for (int p = 0; p < rank; ++p) {
+        if (perm[p] < 0 || perm[p] >= rank || seen[perm[p]]) { set_error("perm is not a permutation"); return TN_EINVAL; }
+        seen[perm[p]] = 1;
+        map[p] = perm[p];
+    }
+    PermArgs a{};
+    fill_perm(a, map, rank);
+    a.src = static_cast<const float2*>(src);
+    a.dst = static_cast<float2*>(dst);
+    a.nb = nb;
+    tn_ctx* none = nullptr;
+    HIPCHK(none, launch_permute(a, static_cast<hipStream_t>(hip_stream)));
+    return TN_OK;
+}
+
+int tn_last_exec_stats(tn_ctx* ctx, tn_exec_stats* out) {
+    if (!ctx || !out) return TN_EINVAL;
+    *out = ctx->last;
+    return TN_OK;
+}
+
+}  // extern "C"

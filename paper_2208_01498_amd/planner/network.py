@@ -1,0 +1,234 @@
+"""Circuit -> tensor network of factors with labelled binary indices.
+
+The network is the paper's circuit network (single- and two-qubit gates as
+rank-2 and rank-4 tensors, the initial |0> and the projection <x| on every
+wire, section on classical simulation around Theorem 2), written so that the
+executor can run it efficiently:
+
+* a wire index (label) starts at a gate whose matrix is not diagonal and ends
+  at the next such gate on that qubit; a diagonal gate (CZ, CP, Z(theta))
+  keeps the index of each of its qubits, so its factor is indexed by its input
+  labels only and one label can be shared by several factors (a hyperedge);
+* a wire still in |0> (no non-diagonal gate yet) is a fixed index 0, which is
+  substituted into every factor that touches it;
+* the last label of each qubit is the output index O_q: it is replaced by
+  the bitstring value x_q at run time, turning it into the batch index b;
+* the absorption of single-qubit gates and projectors into the two-qubit
+  gates (stated as what keeps only the two-qubit gates relevant for the cost)
+  is done by merging factors whenever the merge does not increase the number
+  of indices (rank-non-increasing simplification).
+
+Each factor carries the set of gate indices it was built from, so the same
+tree can be re-evaluated from the circuit by an independent contractor.
+"""
+import numpy as np
+
+FIXED0 = -1
+
+
+class Label:
+    __slots__ = ("id", "dim", "kind", "qubit", "gate")
+
+    def __init__(self, id, dim, kind, qubit, gate):
+        self.id, self.dim, self.kind, self.qubit, self.gate = id, dim, kind, qubit, gate
+
+    def __repr__(self):
+        return f"L{self.id}({self.kind},q{self.qubit},g{self.gate})"
+
+
+class Factor:
+    __slots__ = ("data", "labels", "gates", "pos", "weight")
+
+    def __init__(self, data, labels, gates, pos, weight=1.0):
+        self.data = data
+        self.labels = list(labels)
+        self.gates = set(gates)
+        self.pos = np.asarray(pos, dtype=np.float64)
+        self.weight = weight
+
+
+class Network:
+    """Factors, labels and a global scalar.  Output labels have kind 'out'."""
+
+    def __init__(self, n_qubits, labels, factors, scale, positions):
+        self.n_qubits = n_qubits
+        self.labels = labels          # id -> Label
+        self.factors = factors        # list of Factor
+        self.scale = scale            # complex
+        self.positions = positions    # qubit coordinates
+        self.out_label = {l.qubit: l.id for l in labels.values() if l.kind == "out"}
+
+    def label_users(self):
+        users = {}
+        for i, f in enumerate(self.factors):
+            for l in f.labels:
+                users.setdefault(l, set()).add(i)
+        return users
+
+
+def _is_diag(m):
+    return np.count_nonzero(m - np.diag(np.diag(m))) == 0
+
+
+def _gate_pos(circ, qs):
+    return np.mean([circ.positions[q] for q in qs], axis=0)
+
+
+def build_network(circ, simplify=True):
+    n = circ.n
+    labels = {}
+    factors = []
+    scale = 1.0 + 0.0j
+    scalar_gates = []
+    cur = [FIXED0] * n
+    nxt = [0]
+
+    def new_label(q, g):
+        lid = nxt[0]
+        nxt[0] += 1
+        labels[lid] = Label(lid, 2, "wire", q, g)
+        return lid
+
+    def add_factor(data, labs, gi, qs):
+        nonlocal scale
+        # substitute fixed |0> inputs
+        idx = []
+        keep = []
+        for l in labs:
+            if l == FIXED0:
+                idx.append(0)
+            else:
+                idx.append(slice(None))
+                keep.append(l)
+        data = data[tuple(idx)]
+        if len(set(keep)) != len(keep):
+            raise ValueError("gate acts twice on one wire")
+        if not keep:
+            scale *= complex(data)
+            scalar_gates.append((gi, qs))
+            return
+        factors.append(Factor(np.ascontiguousarray(data, dtype=np.complex128), keep,
+                              {gi}, _gate_pos(circ, qs)))
+
+    for gi, g in enumerate(circ.gates):
+        qs = g.qubits
+        if _is_diag(g.matrix):
+            d = np.diag(g.matrix).reshape((2,) * len(qs))
+            add_factor(d, [cur[q] for q in qs], gi, qs)
+        else:
+            outs = [new_label(q, gi) for q in qs]
+            t = g.matrix.reshape((2,) * (2 * len(qs)))
+            add_factor(t, outs + [cur[q] for q in qs], gi, qs)
+            for q, o in zip(qs, outs):
+                cur[q] = o
+    # outputs
+    for q in range(n):
+        if cur[q] == FIXED0:
+            lid = new_label(q, -1)
+            factors.append(Factor(np.array([1.0, 0.0], dtype=np.complex128), [lid],
+                                  set(), circ.positions[q]))
+            labels[lid].kind = "out"
+        else:
+            labels[cur[q]].kind = "out"
+    net = Network(n, labels, factors, scale, circ.positions)
+    if simplify:
+        simplify_network(net)
+    _attach_scalar_gates(net, circ, scalar_gates)
+    return net
+
+
+def _attach_scalar_gates(net, circ, scalar_gates):
+    """A gate that reduced to a constant (a diagonal gate on wires still in
+    |0>) is recorded in the leaf holding the nearest gate on one of its
+    qubits, so that every gate belongs to exactly one leaf."""
+    owner = {}
+    for i, f in enumerate(net.factors):
+        for g in f.gates:
+            owner[g] = i
+    for gi, qs in scalar_gates:
+        best = None
+        for gj, g in enumerate(circ.gates):
+            if gj in owner and set(g.qubits) & set(qs):
+                key = (abs(gj - gi), gj)
+                if best is None or key < best[0]:
+                    best = (key, owner[gj])
+        if best is None:
+            best = (None, 0)
+        if net.factors:
+            net.factors[best[1]].gates.add(gi)
+
+
+def contract_factors(f, g, keep):
+    """Dense FP64 contraction of two factors, keeping labels in ``keep``."""
+    la, lb = f.labels, g.labels
+    allab = list(dict.fromkeys(la + lb))
+    letters = {l: chr(ord('a') + i) if i < 26 else chr(ord('A') + i - 26)
+               for i, l in enumerate(allab)}
+    out = [l for l in allab if l in keep]
+    spec = "%s,%s->%s" % ("".join(letters[l] for l in la), "".join(letters[l] for l in lb),
+                          "".join(letters[l] for l in out))
+    data = np.einsum(spec, f.data, g.data)
+    wsum = f.weight + g.weight
+    pos = (f.pos * f.weight + g.pos * g.weight) / wsum
+    return Factor(np.ascontiguousarray(data), out, f.gates | g.gates, pos, wsum)
+
+
+def simplify_network(net, max_rank=None):
+    """Merge neighbouring factors while the merge does not raise the rank."""
+    labels = net.labels
+    alive = {i: f for i, f in enumerate(net.factors)}
+    users = {}
+    for i, f in alive.items():
+        for l in f.labels:
+            users.setdefault(l, set()).add(i)
+    nid = len(net.factors)
+    changed = True
+    while changed:
+        changed = False
+        for i in sorted(alive):
+            if i not in alive:
+                continue
+            f = alive[i]
+            best = None
+            for l in f.labels:
+                for j in users[l]:
+                    if j == i or j not in alive:
+                        continue
+                    g = alive[j]
+                    u = set(f.labels) | set(g.labels)
+                    keep = set(x for x in u if labels[x].kind == "out" or
+                               len(users[x] - {i, j}) > 0)
+                    if len(keep) <= max(len(f.labels), len(g.labels)):
+                        key = (len(keep), j)
+                        if best is None or key < best[0]:
+                            best = (key, j, keep)
+            if best is None:
+                continue
+            _, j, keep = best
+            g = alive[j]
+            h = contract_factors(f, g, keep)
+            for x in f.labels:
+                users[x].discard(i)
+            for x in g.labels:
+                users[x].discard(j)
+            del alive[i]
+            del alive[j]
+            alive[nid] = h
+            for x in h.labels:
+                users.setdefault(x, set()).add(nid)
+            nid += 1
+            changed = True
+    # rank-0 factors become scalars
+    facs = []
+    for i in sorted(alive):
+        f = alive[i]
+        if not f.labels:
+            net.scale *= complex(f.data)
+        else:
+            facs.append(f)
+    if facs:
+        for i in sorted(alive):
+            if not alive[i].labels:
+                facs[0].gates |= alive[i].gates
+    net.factors = facs
+    return net

@@ -1,0 +1,137 @@
+"""Plan builder: circuit -> network -> separator hierarchy -> steps -> slices
+-> layout -> TNP1 blob.
+
+TNP1 (little-endian; every integer u32 unless noted):
+  header   "TNP1", version=1, n_qubits, n_labels, n_leaves, n_steps,
+           n_sliced, flags, scale (2 x f64: re, im)
+  labels   n_labels x {dim u8, kind u8 (0 wire, 1 output), pad u16,
+           qubit i32}
+  leaves   n_leaves x {rank, labels[rank] (storage order, C order: first
+           label most significant), n_mat, mat_order[n_mat], n_gates,
+           gate_ids[n_gates], data: 2^rank x (re f64, im f64)}
+           mat_order is the order the leaf is gathered into (its labels
+           minus output and sliced labels); output labels are replaced by
+           the bitstring value of their qubit (giving the batch index b),
+           sliced labels by the slice's bit.
+  sliced   n_sliced label ids; slice s gives sliced label j bit j of s
+  steps    n_steps x {a, b, nA, permA[nA], nB, permB[nB], nC, c_order[nC]}
+           operand ids count leaves first, then step results in order;
+           nA = 0 means A is used as stored, else A is first permuted to
+           permA (same for B); C is written in c_order
+  meta     n_meta, n_meta x f64 (flops per slice per bitstring, log2 width,
+           ...)
+"""
+import math
+import struct
+
+import numpy as np
+
+from .network import build_network
+from .hierarchy import TreeBuilder, tree_steps
+from .slicer import SliceModel
+from .layout import Layout
+from .cost import plan_stats
+
+MAGIC = b"TNP1"
+VERSION = 1
+
+
+class Plan:
+    def __init__(self, circ, net, steps, sliced, leaf_order, step_layout, stats, options):
+        self.circ = circ
+        self.net = net
+        self.steps = steps
+        self.sliced = sliced
+        self.leaf_order = leaf_order
+        self.step_layout = step_layout
+        self.stats = stats
+        self.options = options
+
+    @property
+    def n_slices(self):
+        return 1 << len(self.sliced)
+
+    def order_spec(self):
+        """The contraction order as data for an independent evaluator: leaves
+        as gate-index sets, steps as id pairs, sliced wires as (qubit, gate
+        that starts the wire)."""
+        leaves = [sorted(int(g) for g in f.gates) for f in self.net.factors]
+        sl = [(self.net.labels[l].qubit, self.net.labels[l].gate) for l in self.sliced]
+        return {"leaves": leaves, "steps": [[int(a), int(b)] for a, b in self.steps],
+                "sliced": sl}
+
+    def to_blob(self):
+        net = self.net
+        used = sorted(set(l for f in net.factors for l in f.labels))
+        remap = {l: i for i, l in enumerate(used)}
+        out = bytearray()
+        out += MAGIC
+        out += struct.pack("<7I", VERSION, net.n_qubits, len(used), len(net.factors),
+                           len(self.steps), len(self.sliced), 0)
+        out += struct.pack("<2d", net.scale.real, net.scale.imag)
+        for l in used:
+            lab = net.labels[l]
+            out += struct.pack("<BBHi", lab.dim, 1 if lab.kind == "out" else 0, 0,
+                               lab.qubit)
+        for i, f in enumerate(net.factors):
+            out += struct.pack("<I", len(f.labels))
+            out += struct.pack("<%dI" % len(f.labels), *[remap[l] for l in f.labels])
+            mo = self.leaf_order[i]
+            out += struct.pack("<I", len(mo))
+            out += struct.pack("<%dI" % len(mo), *[remap[l] for l in mo])
+            gs = sorted(f.gates)
+            out += struct.pack("<I", len(gs))
+            out += struct.pack("<%dI" % len(gs), *gs)
+            d = np.ascontiguousarray(f.data, dtype=np.complex128).reshape(-1)
+            out += d.view(np.float64).astype("<f8").tobytes()
+        out += struct.pack("<%dI" % len(self.sliced), *[remap[l] for l in self.sliced])
+        for st in self.step_layout:
+            out += struct.pack("<2I", st["a"], st["b"])
+            for key in ("permA", "permB"):
+                p = st[key] or []
+                out += struct.pack("<I", len(p))
+                out += struct.pack("<%dI" % len(p), *[remap[l] for l in p])
+            oc = st["c_order"]
+            out += struct.pack("<I", len(oc))
+            out += struct.pack("<%dI" % len(oc), *[remap[l] for l in oc])
+        meta = [self.stats["flops_per_b"], self.stats["max_bits"], float(len(self.sliced)),
+                self.stats["total_flops_per_b"]]
+        out += struct.pack("<I", len(meta))
+        out += struct.pack("<%dd" % len(meta), *meta)
+        return bytes(out)
+
+
+def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
+              n_circles=24, trials=1):
+    """Build a plan.  ``n_slices``: number of sliced labels (log2 of the slice
+    count), or None to slice until the widest per-slice intermediate is at
+    most ``target_width`` (log2 elements, batch included)."""
+    net = build_network(circ)
+    best = None
+    for t in range(trials):
+        tb = TreeBuilder(net, np.random.Generator(np.random.PCG64(seed + t)),
+                         bottom=bottom, n_circles=n_circles)
+        root = tb.build()
+        steps = tree_steps(root, len(net.factors))
+        st = plan_stats(net, steps, B=1)
+        if best is None or st["flops"] < best[0]:
+            best = (st["flops"], steps)
+    steps = best[1]
+    sliced = []
+    total = None
+    if steps and (n_slices or target_width is not None):
+        sm = SliceModel(net, steps, B=B)
+        sliced, total, width = sm.greedy(n_slices=n_slices if n_slices else None,
+                                         target_width=target_width)
+    lay = Layout(net, steps, sliced)
+    leaf_order, step_layout = lay.run()
+    st = plan_stats(net, steps, sliced=sliced, B=1)
+    if total is None:
+        total = st["flops"] * (1 << len(sliced))
+    stats = dict(flops_per_b=st["flops"], max_bits=st["max_bits"],
+                 total_flops_per_b=total / B if sliced else st["flops"],
+                 permute_elems=lay.permute_elems, n_leaves=len(net.factors),
+                 n_steps=len(steps))
+    return Plan(circ, net, steps, sliced, leaf_order, step_layout, stats,
+                dict(n_slices=n_slices, target_width=target_width, B=B, bottom=bottom,
+                     seed=seed))

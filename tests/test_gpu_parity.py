@@ -1,0 +1,152 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle."""
+import numpy as np
+import pytest
+
+from circuits import (make_config, lattice_circuit, stack3d_circuit, iqp_lattice_circuit,
+                      random_bitstrings, mirror, product_circuit)
+from oracle import statevector_amplitudes, pairwise_amplitudes
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-5, 2: 1e-3}
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2208_01498_amd import binding as B
+    e = B.Engine(0, arena_bytes=256 << 20)
+    yield e
+    e.close()
+
+
+def _plan(circ, ns=0, B=8, **kw):
+    from paper_2208_01498_amd.planner.plan import make_plan
+    return make_plan(circ, n_slices=ns, B=B, **kw)
+
+
+def _relerr(got, ref, n):
+    """|a - a_ref| / |a_ref| for results not in the far Porter-Thomas tail,
+    |a - a_ref| / 2^{-n/2} for the rest."""
+    scale = 2.0 ** (-n / 2)
+    den = np.where(np.abs(ref) >= 1e-2 * scale, np.abs(ref), scale)
+    return np.abs(got - ref) / den
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+@pytest.mark.parametrize("ns", [0, 3])
+def test_cfg1_all_bitstrings(eng, prec, ns):
+    circ, words, _ = make_config("cfg1")
+    print("case cfg1 prec", prec, "slices", ns, flush=True)
+    plan = _plan(circ, ns, B=len(words))
+    p = eng.load(plan.to_blob())
+    got = eng.amplitudes(p, words, prec)
+    ref = statevector_amplitudes(circ, words)
+    err = _relerr(got, ref, circ.n)
+    print("max rel err", err.max(), flush=True)
+    assert err.max() <= TOL[prec]
+
+
+FAMILIES = [
+    ("sqrt_cz_3x4_d6", lambda: lattice_circuit(3, 4, 6, 201, "sqrt", "cz")),
+    ("sqrt_fsim_3x3_d5", lambda: lattice_circuit(3, 3, 5, 202, "sqrt", "fsim")),
+    ("haar_cz_4x4_d10", lambda: lattice_circuit(4, 4, 10, 203, "haar", "cz")),
+    ("stack_2x2x3", lambda: stack3d_circuit(2, 2, 3, 6, 204)),
+    ("iqp_3x4", lambda: iqp_lattice_circuit(3, 4, 205)),
+    ("product_8", lambda: product_circuit(8, 3, 206)),
+]
+
+
+@pytest.mark.parametrize("name,mk", FAMILIES, ids=[f[0] for f in FAMILIES])
+@pytest.mark.parametrize("ns", [0, 2])
+def test_families_vs_statevector(eng, name, mk, ns):
+    circ = mk()
+    words = random_bitstrings(circ.n, 37, 300)       # odd batch
+    print("case", name, "slices", ns, flush=True)
+    plan = _plan(circ, ns, B=len(words))
+    p = eng.load(plan.to_blob())
+    got = eng.amplitudes(p, words, 0)
+    ref = statevector_amplitudes(circ, words)
+    err = _relerr(got, ref, circ.n)
+    assert err.max() <= 1e-5, err.max()
+
+
+def test_chunking_is_bitwise_invariant():
+    """A small arena forces chunks of a few bitstrings; results must be
+    bitwise identical to a single-chunk run."""
+    from paper_2208_01498_amd import binding as B
+    circ = lattice_circuit(4, 4, 8, 211, "haar", "cz")
+    words = random_bitstrings(16, 64, 212)
+    plan = _plan(circ, 2, B=64)
+    blob = plan.to_blob()
+    big = B.Engine(0, arena_bytes=256 << 20)
+    small = B.Engine(0, arena_bytes=2 << 20)
+    try:
+        a = big.amplitudes(big.load(blob), words, 0)
+        st_big = B.tn_last_exec_stats(big.ctx)
+        b = small.amplitudes(small.load(blob), words, 0)
+        st_small = B.tn_last_exec_stats(small.ctx)
+        print("chunks", st_big["n_chunks"], st_small["n_chunks"], flush=True)
+        assert st_small["n_chunks"] > st_big["n_chunks"]
+        assert np.array_equal(a, b)
+    finally:
+        big.close()
+        small.close()
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+GEMM_SHAPES = [(1, 1, 1), (4, 2, 1), (32, 16, 8), (64, 64, 8), (128, 128, 8), (256, 128, 64),
+               (128, 256, 16), (64, 32, 2), (512, 64, 128), (1024, 1024, 32)]
+
+
+@pytest.mark.parametrize("M,N,K", GEMM_SHAPES)
+@pytest.mark.parametrize("tA,tB", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("prec", [0, 2])
+def test_kernel_cgemm(M, N, K, tA, tB, prec):
+    import torch
+    from paper_2208_01498_amd import binding as B
+    rng = np.random.Generator(np.random.PCG64(M * 7 + N * 3 + K + tA * 2 + tB))
+    nbatch, nb = 3, 2
+    A = (rng.standard_normal((nb, nbatch, M, K)) + 1j * rng.standard_normal((nb, nbatch, M, K))).astype(np.complex64)
+    Bm = (rng.standard_normal((nbatch, K, N)) + 1j * rng.standard_normal((nbatch, K, N))).astype(np.complex64)
+    As = np.swapaxes(A, -1, -2).copy() if tA else A
+    Bs = np.swapaxes(Bm, -1, -2).copy() if tB else Bm
+    dA, dB = _dev(As.view(np.float32)), _dev(Bs.view(np.float32))
+    dC = torch.zeros(nb * nbatch * M * N * 2, dtype=torch.float32, device="cuda")
+    print("case gemm", M, N, K, tA, tB, prec, flush=True)
+    B.tn_kernel_cgemm(dA.data_ptr(), dB.data_ptr(), dC.data_ptr(), M, N, K, tA, tB, nbatch, nb,
+                      sAb=nbatch * M * K, sBb=0, sCb=nbatch * M * N, sAi=M * K, sBi=K * N,
+                      sCi=M * N, precision=prec)
+    torch.cuda.synchronize()
+    C = dC.cpu().numpy().view(np.complex64).reshape(nb, nbatch, M, N)
+    ref = np.matmul(A.astype(np.complex128), Bm.astype(np.complex128)[None])
+    scale = np.sqrt(K) * 2
+    err = np.max(np.abs(C - ref)) / scale
+    assert err <= (1e-5 if prec == 0 else 1e-3), err
+
+
+@pytest.mark.parametrize("rank,nb", [(1, 1), (3, 5), (8, 2), (12, 3), (17, 1), (20, 2)])
+def test_kernel_permute(rank, nb):
+    import torch
+    from paper_2208_01498_amd import binding as B
+    rng = np.random.Generator(np.random.PCG64(rank * 31 + nb))
+    perm = [int(x) for x in rng.permutation(rank)]
+    x = (rng.standard_normal((nb, 1 << rank)) + 1j * rng.standard_normal((nb, 1 << rank))).astype(np.complex64)
+    dx = _dev(x.view(np.float32))
+    dy = torch.zeros_like(dx)
+    print("case permute", rank, nb, perm, flush=True)
+    B.tn_kernel_permute(dx.data_ptr(), dy.data_ptr(), rank, perm, nb)
+    torch.cuda.synchronize()
+    y = dy.cpu().numpy().view(np.complex64).reshape(nb, 1 << rank)
+    # destination bit p takes source bit perm[p]: as C-order axes (axis 0 is
+    # the most significant bit), destination axis rank-1-p is source axis
+    # rank-1-perm[p]
+    src = x.reshape((nb,) + (2,) * rank)
+    axes = [0] + [1 + (rank - 1 - perm[rank - 1 - a]) for a in range(rank)]
+    want = np.transpose(src, axes).reshape(nb, 1 << rank)
+    assert np.array_equal(y, want)
