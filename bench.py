@@ -1,0 +1,160 @@
+"""Benchmark: amplitudes/s of the 8x8 depth-16 random circuit (Haar SU(2) +
+CZ, 2^10 slices, 64 bitstrings) on one MI355X, with the roofline of the
+dominant GEMM kernel and the CPU oracle timed beside it.
+
+One step = one tn_contract_amplitudes call over the whole batch (all slices,
+all chunks), inputs resident: the plan is built and loaded before timing.
+
+  python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3]
+                  [--config cfg3] [--batch B] [--slices S] [--width W]
+                  [--no-cpu]
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32": 157.3e12, "bf16x3": 2516.6e12}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(circ, word, seconds=20.0, width=24, seed=0):
+    """The oracle (pairwise contraction in complex128, plan order imported
+    as data) on a bounded sample: slices of one amplitude under a slicing of
+    the same network whose widest tensor has 2^width entries, timed until
+    ``seconds`` pass; the rate is scaled to amplitudes/s by the slice count."""
+    import numpy as np
+    from oracle.pairwise import OracleNetwork, _restrict, _evaluate
+    from paper_2208_01498_amd.planner.plan import make_plan
+    plan = make_plan(circ, n_slices=None, target_width=width, B=1, seed=seed)
+    spec = plan.order_spec()
+    net = OracleNetwork(circ, word)
+    labels = net.labels_of_slice_spec(spec["sliced"])
+    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    t0 = time.perf_counter()
+    done = 0
+    while True:
+        s = done
+        fixed = {l: (s >> j) & 1 for j, l in enumerate(labels)}
+        _evaluate(_restrict(net.pieces, fixed), spec)
+        done += 1
+        if time.perf_counter() - t0 >= seconds or done >= (1 << len(labels)):
+            break
+    el = time.perf_counter() - t0
+    per_amp = el / done * (1 << len(labels))
+    return {"value": 1.0 / per_amp, "unit": "amplitudes/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "%d of 2^%d slices of one amplitude (bitstring 0 of the batch), "
+                      "oracle pairwise contraction in plan order, %.1f s; scaled by the "
+                      "slice count" % (done, len(labels), el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="cfg3")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--batch", type=int, default=None)
+    ap.add_argument("--slices", type=int, default=10)
+    ap.add_argument("--width", type=float, default=None)
+    ap.add_argument("--arena-gb", type=float, default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(slices would shard across GPUs with one all-reduce of the FP64 sums)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from circuits import make_config
+    from paper_2208_01498_amd.planner.plan import make_plan
+    from paper_2208_01498_amd import binding as B
+
+    circ, words, info = make_config(args.config)
+    if args.batch:
+        words = words[:args.batch]
+    nb = len(words)
+    t = time.perf_counter()
+    plan = make_plan(circ, n_slices=args.slices, target_width=args.width, B=nb, seed=args.seed)
+    blob = plan.to_blob()
+    log("plan built in %.1f s: %d leaves, %d steps, %d sliced labels" %
+        (time.perf_counter() - t, plan.stats["n_leaves"], plan.stats["n_steps"], len(plan.sliced)))
+    free, total = torch.cuda.mem_get_info(0)
+    arena = int((args.arena_gb * 2 ** 30) if args.arena_gb else (free - (6 << 30)))
+    eng = B.Engine(0, arena_bytes=arena)
+    p = eng.load(blob)
+    pinfo = B.tn_plan_info(p)
+    log("plan info", pinfo)
+    prec = B.PRECISIONS[args.precision]
+    for _ in range(args.warmup):
+        eng.amplitudes(p, words, prec)
+        log("warmup step done", B.tn_last_exec_stats(eng.ctx)["chunk"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        amps = eng.amplitudes(p, words, prec)
+        log("timed step %d done" % k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = B.tn_last_exec_stats(eng.ctx)
+    el = t1 - t0
+    value = nb * args.steps / el
+    # per-kernel timing on the executing stream (separate profiled run)
+    B.tn_ctx_set_profiling(eng.ctx, 1)
+    eng.amplitudes(p, words, prec)
+    prof = B.tn_last_exec_stats(eng.ctx)
+    B.tn_ctx_set_profiling(eng.ctx, 0)
+    kinds = B.KERNEL_CLASSES
+    per_kind = {kinds[i]: {"launches": prof["launches"][i], "ms": prof["time_ms"][i],
+                           "flops": prof["flops"][i], "bytes": prof["bytes"][i]}
+                for i in range(5)}
+    log("per kernel class", json.dumps(per_kind))
+    dom = max(range(3), key=lambda i: prof["time_ms"][i])
+    ms = prof["time_ms"][dom]
+    achieved = prof["flops"][dom] / (ms * 1e-3) if ms > 0 else 0.0
+    peak = PEAK[args.precision]
+    roofline = {"bound": "mfma", "kernel": kinds[dom],
+                "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None,
+                "avg_launch_ms": ms / max(1, prof["launches"][dom]),
+                "gemm_time_frac": sum(prof["time_ms"][:3]) / max(1e-9, sum(prof["time_ms"]))}
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(circ, int(words[0]), seconds=args.cpu_seconds)
+    out = {
+        "metric": "amplitudes/s, 8x8 depth-16 circuit (2^10 slices, 64 bitstrings)",
+        "value": value, "unit": "amplitudes/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64/f32-mfma" if args.precision == "fp32" else "bf16x3-mfma/f32-acc",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.config, info["desc"]), "batch": nb,
+                   "slices": 1 << len(plan.sliced), "precision": args.precision,
+                   "chunk": st["chunk"], "n_chunks": st["n_chunks"],
+                   "plan_flops_per_amplitude": pinfo["flops_total_per_b"]},
+        "roofline": roofline,
+        "achieved_plan_tflops": pinfo["flops_total_per_b"] * nb * args.steps / el / 1e12,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    eng.close()
+
+
+if __name__ == "__main__":
+    main()

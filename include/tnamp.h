@@ -157,7 +157,19 @@ typedef struct tn_exec_stats {
     int32_t n_chunks;
     double algorithmic_flops;         /* sum over executed steps     */
     double permute_bytes;             /* 16 bytes per permuted element */
+    /* per kernel class (0 small GEMM, 1 MFMA GEMM 64x64 tile, 2 MFMA GEMM
+     * 128x128 tile, 3 permute, 4 leaf gather): launches, summed device time
+     * from HIP events recorded around each launch on the executing stream
+     * (only when profiling is on), algorithmic flops (GEMM) and algorithmic
+     * bytes (permute: 16 per element; gather: 8 per written element) */
+    int64_t launches[5];
+    double time_ms[5];
+    double flops[5];
+    double bytes[5];
 } tn_exec_stats;
+
+/* Turn per-launch event timing of tn_contract_amplitudes on (1) or off (0). */
+int tn_ctx_set_profiling(tn_ctx* ctx, int32_t on);
 int tn_last_exec_stats(tn_ctx* ctx, tn_exec_stats* out);
 
 /*

@@ -5,9 +5,10 @@ The network follows the paper's construction of a circuit as a tensor network
 (section on classical simulation of quantum circuits, around Theorem 2):
 every gate is a tensor over its input and output wires (rank 2 for single-
 qubit gates, rank 4 for two-qubit gates, T[o1,o2,i1,i2] = G[2o1+o2, 2i1+i2]),
-the initial state contributes e_0 on every input wire and the projection onto
-|x> contributes e_{x_q} on every output wire.  Nothing is absorbed, split or
-pre-contracted across gates: every piece stays a plain dense tensor.
+the initial state |0> fixes every input wire to 0 and the projection onto
+<x| fixes every output wire to x_q (each piece carrying such a wire is
+indexed at that value).  Nothing is absorbed, split or pre-contracted across
+gates: every piece stays a plain dense tensor.
 
 One optional, exact re-labelling: with ``diagonal_hyperedges`` a gate whose
 matrix is diagonal keeps its wires' labels (output wire = input wire), so its
@@ -33,10 +34,6 @@ values are summed in complex128.
 import itertools
 import numpy as np
 
-_E = (np.array([1.0, 0.0], dtype=np.complex128),
-      np.array([0.0, 1.0], dtype=np.complex128))
-
-
 def _is_diag(m):
     return np.count_nonzero(m - np.diag(np.diag(m))) == 0
 
@@ -44,9 +41,8 @@ def _is_diag(m):
 class OracleNetwork:
     """Pieces (array, labels, gate tag) of the network of one amplitude.
 
-    Tag of a gate piece and of the boundary vectors attached to it is the
-    gate's index in the circuit; qubits that no gate touches contribute the
-    scalar <x_q|0> to ``const``.
+    The tag of a piece is its gate's index in the circuit; a qubit whose wire
+    never leaves |0> contributes the scalar <x_q|0> to ``const``.
     """
 
     def __init__(self, circ, word, diagonal_hyperedges=True):
@@ -56,11 +52,9 @@ class OracleNetwork:
         self.const = 1.0 + 0.0j
         nxt = itertools.count()
         cur = {}
-        first = {}
         last = {}
         for gi, g in enumerate(circ.gates):
             for q in g.qubits:
-                first.setdefault(q, gi)
                 last[q] = gi
         for q in range(n):
             cur[q] = next(nxt)
@@ -81,15 +75,20 @@ class OracleNetwork:
                     cur[q] = o
             for q in qs:
                 self.wire_after[(q, gi)] = cur[q]
-            for q in qs:
-                if first[q] == gi:
-                    self.pieces.append([_E[0], [self.wire_after[(q, -1)]], gi])
+        # the initial |0> and the projection onto <x| fix the first and the
+        # last wire of every qubit: each piece carrying such a wire is
+        # indexed at that value (the paper absorbs the projectors into the
+        # gate tensors); a qubit no gate touches contributes <x_q|0>
+        fixed = {}
         for q in range(n):
             xq = (int(word) >> q) & 1
-            if q in last:
-                self.pieces.append([_E[xq], [cur[q]], last[q]])
+            fixed[self.wire_after[(q, -1)]] = 0
+            if cur[q] != self.wire_after[(q, -1)]:
+                fixed[cur[q]] = xq
             elif xq == 1:
+                # the wire never leaves |0> (no gate, or diagonal gates only)
                 self.const = 0.0 + 0.0j
+        self.pieces = _restrict(self.pieces, fixed)
 
     def labels_of_slice_spec(self, spec):
         return [self.wire_after[(q, g)] for (q, g) in spec]

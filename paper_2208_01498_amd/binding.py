@@ -22,7 +22,7 @@ PRECISIONS = {"fp32": TN_FP32_4M, "fp32_3m": TN_FP32_3M, "bf16x3": TN_SPLIT_BF16
 EXPORTED = ["tn_ctx_create", "tn_ctx_destroy", "tn_plan_load", "tn_plan_validate",
             "tn_plan_info", "tn_plan_unload", "tn_contract_amplitudes", "tn_submit",
             "tn_poll", "tn_cancel", "tn_server_config", "tn_server_stop",
-            "tn_last_exec_stats", "tn_kernel_cgemm", "tn_kernel_permute", "tn_last_error"]
+            "tn_last_exec_stats", "tn_ctx_set_profiling", "tn_kernel_cgemm", "tn_kernel_permute", "tn_last_error"]
 
 
 class TnError(RuntimeError):
@@ -51,7 +51,11 @@ class tn_exec_stats(ctypes.Structure):
                 ("kernels_gather", ctypes.c_int64), ("steps_executed", ctypes.c_int64),
                 ("steps_reused", ctypes.c_int64), ("chunk", ctypes.c_int32),
                 ("n_chunks", ctypes.c_int32), ("algorithmic_flops", ctypes.c_double),
-                ("permute_bytes", ctypes.c_double)]
+                ("permute_bytes", ctypes.c_double), ("launches", ctypes.c_int64 * 5),
+                ("time_ms", ctypes.c_double * 5), ("flops", ctypes.c_double * 5),
+                ("bytes", ctypes.c_double * 5)]
+
+KERNEL_CLASSES = ["cgemm_small", "cgemm_mfma_64x64", "cgemm_mfma_128x128", "permute", "gather"]
 
 
 _lib = None
@@ -81,6 +85,7 @@ def load_library(path=LIB_PATH):
         "tn_server_config": [vp, i32, i32],
         "tn_server_stop": [vp],
         "tn_last_exec_stats": [vp, ctypes.POINTER(tn_exec_stats)],
+        "tn_ctx_set_profiling": [vp, i32],
         "tn_kernel_cgemm": [vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, ctypes.c_int64,
                             ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                             ctypes.c_int64, i32, vp],
@@ -199,7 +204,15 @@ def tn_kernel_permute(src, dst, rank, perm, nb=1, stream=None):
 def tn_last_exec_stats(ctx):
     st = tn_exec_stats()
     _check(load_library().tn_last_exec_stats(ctx, ctypes.byref(st)))
-    return {k: getattr(st, k) for k, _ in st._fields_}
+    out = {}
+    for k, _ in st._fields_:
+        v = getattr(st, k)
+        out[k] = list(v) if hasattr(v, "__len__") else v
+    return out
+
+
+def tn_ctx_set_profiling(ctx, on):
+    _check(load_library().tn_ctx_set_profiling(ctx, 1 if on else 0))
 
 
 class Engine:

@@ -101,8 +101,46 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
     const int S = (int)p.sliced.size();
     const uint64_t nslices = 1ull << S;
     const int nL = (int)p.leaves.size();
-    std::vector<double> host_acc;
     es.chunk = chunk;
+    // event timing: pairs (start, end) per launch, harvested at every chunk
+    // end and whenever the pool is used up
+    const bool prof = ctx && ctx->profile && stats;
+    struct Rec { int kind; double flops, bytes; };
+    std::vector<Rec> recs;
+    size_t ev_used = 0;
+    auto harvest = [&]() -> int {
+        if (!prof || recs.empty()) return TN_OK;
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+        for (size_t i = 0; i < recs.size(); ++i) {
+            float ms = 0.f;
+            HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->events[2 * i], ctx->events[2 * i + 1]));
+            es.time_ms[recs[i].kind] += ms;
+        }
+        recs.clear();
+        ev_used = 0;
+        return TN_OK;
+    };
+    auto ev_begin = [&]() -> int {
+        if (!prof) return TN_OK;
+        if (ev_used + 2 > 8192) { int rc = harvest(); if (rc) return rc; }
+        while (ctx->events.size() < ev_used + 2) {
+            hipEvent_t e;
+            HIPCHK(ctx, hipEventCreate(&e));
+            ctx->events.push_back(e);
+        }
+        HIPCHK(ctx, hipEventRecord(ctx->events[ev_used], stream));
+        return TN_OK;
+    };
+    auto ev_end = [&](int kind, double flops, double bytes) -> int {
+        es.launches[kind]++;
+        es.flops[kind] += flops;
+        es.bytes[kind] += bytes;
+        if (!prof) return TN_OK;
+        HIPCHK(ctx, hipEventRecord(ctx->events[ev_used + 1], stream));
+        recs.push_back({kind, flops, bytes});
+        ev_used += 2;
+        return TN_OK;
+    };
     for (int c0 = 0; c0 < nb; c0 += chunk) {
         const int cb = std::min(chunk, nb - c0);
         es.n_chunks++;
@@ -134,9 +172,11 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                 for (int i = 0; i < lf.n_mat; ++i) g.mat_src[i] = lf.mat_src[i];
                 for (int i = 0; i < lf.n_out; ++i) { g.out_src[i] = lf.out_src[i]; g.out_qubit[i] = lf.out_qubit[i]; }
                 for (int i = 0; i < lf.n_sl; ++i) { g.sl_src[i] = lf.sl_src[i]; g.sl_bit[i] = lf.sl_bit[i]; }
+                int rc0 = ev_begin();
+                if (rc0) return rc0;
                 HIPCHK(ctx, launch_gather(g, stream));
                 es.kernels_gather++;
-                return TN_OK;
+                return ev_end(4, 0.0, 8.0 * std::ldexp(1.0, g.n_mat) * g.nb);
             };
             if (p.steps.empty()) {
                 int rc = gather(0);
@@ -160,9 +200,13 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                     a.src = pa;
                     a.dst = reinterpret_cast<float2*>(ws + mp.permA_off[si]);
                     a.nb = st.hbA ? cb : 1;
+                    rc = ev_begin();
+                    if (rc) return rc;
                     HIPCHK(ctx, launch_permute(a, stream));
                     es.kernels_permute++;
                     es.permute_bytes += 16.0 * std::ldexp(1.0, a.rank) * a.nb;
+                    rc = ev_end(3, 0.0, 16.0 * std::ldexp(1.0, a.rank) * a.nb);
+                    if (rc) return rc;
                     pa = a.dst;
                 }
                 if (st.permB) {
@@ -171,9 +215,13 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                     a.src = pb;
                     a.dst = reinterpret_cast<float2*>(ws + mp.permB_off[si]);
                     a.nb = st.hbB ? cb : 1;
+                    rc = ev_begin();
+                    if (rc) return rc;
                     HIPCHK(ctx, launch_permute(a, stream));
                     es.kernels_permute++;
                     es.permute_bytes += 16.0 * std::ldexp(1.0, a.rank) * a.nb;
+                    rc = ev_end(3, 0.0, 16.0 * std::ldexp(1.0, a.rank) * a.nb);
+                    if (rc) return rc;
                     pb = a.dst;
                 }
                 const long long nbat = 1ll << st.batch_bits;
@@ -198,10 +246,15 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                 g.sCb = nbat * M * N; g.sCi = M * N;
                 g.nbatch = (int)nbat;
                 g.nb = nbC;
+                rc = ev_begin();
+                if (rc) return rc;
                 HIPCHK(ctx, launch_gemm(g, precision, stream));
                 es.kernels_gemm++;
                 es.steps_executed++;
                 es.algorithmic_flops += st.flops_per_b * nbC;
+                rc = ev_end(gemm_kind(g, precision), st.flops_per_b * nbC,
+                            8.0 * ((double)nbat * (M * K * (st.hbA ? nbC : 1) + K * N * (st.hbB ? nbC : 1) + M * N * nbC)));
+                if (rc) return rc;
             }
             const int root = p.root;
             HIPCHK(ctx, launch_accumulate(d_acc, tensor_ptr(root), cb, p.has_b[root], stream));
@@ -209,6 +262,8 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
         HIPCHK(ctx, launch_finalize(d_acc, cb, p.scale.real(), p.scale.imag(), stream));
         HIPCHK(ctx, hipMemcpyAsync(out + 2 * (size_t)c0, d_acc, sizeof(double2) * cb, hipMemcpyDeviceToHost, stream));
         HIPCHK(ctx, hipStreamSynchronize(stream));
+        int rch = harvest();
+        if (rch) return rch;
     }
     if (stats) *stats = es;
     return TN_OK;
@@ -263,6 +318,7 @@ int tn_ctx_destroy(tn_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipStreamDestroy(ctx->stream);
+    for (auto e : ctx->events) (void)hipEventDestroy(e);
     if (ctx->own_arena) (void)hipFree(ctx->arena);
     delete ctx;
     return TN_OK;
@@ -407,6 +463,12 @@ int tn_kernel_permute(const void* src, void* dst, int32_t rank, const int32_t* p
     a.nb = nb;
     tn_ctx* none = nullptr;
     HIPCHK(none, launch_permute(a, static_cast<hipStream_t>(hip_stream)));
+    return TN_OK;
+}
+
+int tn_ctx_set_profiling(tn_ctx* ctx, int32_t on) {
+    if (!ctx) return TN_EINVAL;
+    ctx->profile = on != 0;
     return TN_OK;
 }
 

@@ -172,6 +172,9 @@ struct tn_ctx {
     std::vector<std::unique_ptr<tn::Slot>> slots;
     // arena sub-allocation for served batches: (offset, size) free list
     std::map<size_t, size_t> free_list;
+    // per-launch event timing (blocking calls only)
+    bool profile = false;
+    std::vector<hipEvent_t> events;
 };
 
 namespace tn {

@@ -76,12 +76,15 @@ def test_chunking_is_bitwise_invariant():
     """A small arena forces chunks of a few bitstrings; results must be
     bitwise identical to a single-chunk run."""
     from paper_2208_01498_amd import binding as B
-    circ = lattice_circuit(4, 4, 8, 211, "haar", "cz")
-    words = random_bitstrings(16, 64, 212)
+    circ = lattice_circuit(5, 5, 10, 211, "haar", "cz")
+    words = random_bitstrings(25, 64, 212)
     plan = _plan(circ, 2, B=64)
     blob = plan.to_blob()
+    info = B.tn_plan_validate(blob)
+    small_bytes = max(1 << 20, info["peak_bytes_fixed"] + 12 * info["peak_bytes_per_b"])
+    print("arena for ~12 bitstrings", small_bytes, flush=True)
     big = B.Engine(0, arena_bytes=256 << 20)
-    small = B.Engine(0, arena_bytes=2 << 20)
+    small = B.Engine(0, arena_bytes=int(small_bytes))
     try:
         a = big.amplitudes(big.load(blob), words, 0)
         st_big = B.tn_last_exec_stats(big.ctx)
