@@ -123,9 +123,9 @@ def main():
     kinds = B.KERNEL_CLASSES
     per_kind = {kinds[i]: {"launches": prof["launches"][i], "ms": prof["time_ms"][i],
                            "flops": prof["flops"][i], "bytes": prof["bytes"][i]}
-                for i in range(5)}
+                for i in range(6)}
     log("per kernel class", json.dumps(per_kind))
-    dom = max(range(3), key=lambda i: prof["time_ms"][i])
+    dom = max(range(4), key=lambda i: prof["time_ms"][i])
     ms = prof["time_ms"][dom]
     achieved = prof["flops"][dom] / (ms * 1e-3) if ms > 0 else 0.0
     peak = PEAK[args.precision]
@@ -133,7 +133,7 @@ def main():
                 "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None,
                 "avg_launch_ms": ms / max(1, prof["launches"][dom]),
-                "gemm_time_frac": sum(prof["time_ms"][:3]) / max(1e-9, sum(prof["time_ms"]))}
+                "gemm_time_frac": sum(prof["time_ms"][:4]) / max(1e-9, sum(prof["time_ms"]))}
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(circ, int(words[0]), seconds=args.cpu_seconds)

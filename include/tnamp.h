@@ -157,15 +157,17 @@ typedef struct tn_exec_stats {
     int32_t n_chunks;
     double algorithmic_flops;         /* sum over executed steps     */
     double permute_bytes;             /* 16 bytes per permuted element */
-    /* per kernel class (0 small GEMM, 1 MFMA GEMM 64x64 tile, 2 MFMA GEMM
-     * 128x128 tile, 3 permute, 4 leaf gather): launches, summed device time
-     * from HIP events recorded around each launch on the executing stream
-     * (only when profiling is on), algorithmic flops (GEMM) and algorithmic
-     * bytes (permute: 16 per element; gather: 8 per written element) */
-    int64_t launches[5];
-    double time_ms[5];
-    double flops[5];
-    double bytes[5];
+    /* per kernel class (0 dot-product GEMM for tiny outputs, 1 MFMA GEMM
+     * 64x64 tile, 2 MFMA GEMM 128x128 tile, 3 MFMA GEMM 128x16 tile, 4
+     * permute, 5 leaf gather): launches, summed device time from HIP events
+     * recorded around each launch on the executing stream (only when
+     * profiling is on), algorithmic flops (GEMM: 8 per complex multiply-add)
+     * and algorithmic bytes (GEMM: operands read once and C written once;
+     * permute: 16 per element; gather: 8 per written element) */
+    int64_t launches[6];
+    double time_ms[6];
+    double flops[6];
+    double bytes[6];
 } tn_exec_stats;
 
 /* Turn per-launch event timing of tn_contract_amplitudes on (1) or off (0). */
@@ -181,9 +183,11 @@ int tn_last_exec_stats(tn_ctx* ctx, tn_exec_stats* out);
  *   C[ob*sCb + ib*sCi + m*N + n] = sum_k A(m,k) * B(k,n)
  *   A(m,k) = A[ob*sAb + ib*sAi + (transA ? k*M + m : m*K + k)]
  *   B(k,n) = B[ob*sBb + ib*sBi + (transB ? n*K + k : k*N + n)]
- *   strides in complex elements; sAb or sBb may be 0 (broadcast).
- *   precision TN_FP32_4M or TN_SPLIT_BF16.  Returns TN_EINVAL for
- *   non-positive sizes, TN_EDEVICE on a launch error.
+ *   strides in complex elements; sAb or sBb may be 0 (broadcast); M, N, K
+ *   powers of two.  precision TN_FP32_4M or TN_SPLIT_BF16.  `scratch`:
+ *   device memory for split-K partial sums (see
+ *   tn_kernel_cgemm_scratch_bytes).  Returns TN_EINVAL for bad sizes or too
+ *   little scratch, TN_EDEVICE on a launch error.
  * tn_kernel_permute: bit permutation of the element index:
  *   dst[b*2^rank + sum_p bit_{perm[p]}(i) << p] = src[b*2^rank + i]
  *   (destination bit p takes source bit perm[p]); rank <= 40, perm must be a
@@ -192,7 +196,11 @@ int tn_last_exec_stats(tn_ctx* ctx, tn_exec_stats* out);
 int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N, int32_t K,
                     int32_t transA, int32_t transB, int32_t nbatch, int32_t nb,
                     int64_t sAb, int64_t sBb, int64_t sCb, int64_t sAi, int64_t sBi,
-                    int64_t sCi, int32_t precision, void* hip_stream);
+                    int64_t sCi, int32_t precision, void* scratch, size_t scratch_bytes,
+                    void* hip_stream);
+/* Device scratch tn_kernel_cgemm needs for this shape (0 when the shape runs
+ * without a K split); a call with less returns TN_EINVAL. */
+size_t tn_kernel_cgemm_scratch_bytes(int32_t M, int32_t N, int32_t K, int32_t nbatch, int32_t nb);
 int tn_kernel_permute(const void* src, void* dst, int32_t rank, const int32_t* perm,
                       int32_t nb, void* hip_stream);
 

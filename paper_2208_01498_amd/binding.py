@@ -22,7 +22,8 @@ PRECISIONS = {"fp32": TN_FP32_4M, "fp32_3m": TN_FP32_3M, "bf16x3": TN_SPLIT_BF16
 EXPORTED = ["tn_ctx_create", "tn_ctx_destroy", "tn_plan_load", "tn_plan_validate",
             "tn_plan_info", "tn_plan_unload", "tn_contract_amplitudes", "tn_submit",
             "tn_poll", "tn_cancel", "tn_server_config", "tn_server_stop",
-            "tn_last_exec_stats", "tn_ctx_set_profiling", "tn_kernel_cgemm", "tn_kernel_permute", "tn_last_error"]
+            "tn_last_exec_stats", "tn_ctx_set_profiling", "tn_kernel_cgemm", "tn_kernel_cgemm_scratch_bytes", "tn_kernel_permute",
+            "tn_last_error"]
 
 
 class TnError(RuntimeError):
@@ -51,11 +52,12 @@ class tn_exec_stats(ctypes.Structure):
                 ("kernels_gather", ctypes.c_int64), ("steps_executed", ctypes.c_int64),
                 ("steps_reused", ctypes.c_int64), ("chunk", ctypes.c_int32),
                 ("n_chunks", ctypes.c_int32), ("algorithmic_flops", ctypes.c_double),
-                ("permute_bytes", ctypes.c_double), ("launches", ctypes.c_int64 * 5),
-                ("time_ms", ctypes.c_double * 5), ("flops", ctypes.c_double * 5),
-                ("bytes", ctypes.c_double * 5)]
+                ("permute_bytes", ctypes.c_double), ("launches", ctypes.c_int64 * 6),
+                ("time_ms", ctypes.c_double * 6), ("flops", ctypes.c_double * 6),
+                ("bytes", ctypes.c_double * 6)]
 
-KERNEL_CLASSES = ["cgemm_small", "cgemm_mfma_64x64", "cgemm_mfma_128x128", "permute", "gather"]
+KERNEL_CLASSES = ["cgemm_dot", "cgemm_mfma_64x64", "cgemm_mfma_128x128", "cgemm_mfma_128x16",
+                  "permute", "gather"]
 
 
 _lib = None
@@ -88,13 +90,15 @@ def load_library(path=LIB_PATH):
         "tn_ctx_set_profiling": [vp, i32],
         "tn_kernel_cgemm": [vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, ctypes.c_int64,
                             ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
-                            ctypes.c_int64, i32, vp],
+                            ctypes.c_int64, i32, vp, sz, vp],
         "tn_kernel_permute": [vp, vp, i32, ctypes.POINTER(ctypes.c_int32), i32, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int
+    lib.tn_kernel_cgemm_scratch_bytes.argtypes = [i32, i32, i32, i32, i32]
+    lib.tn_kernel_cgemm_scratch_bytes.restype = ctypes.c_size_t
     lib.tn_last_error.argtypes = []
     lib.tn_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -188,11 +192,17 @@ def tn_server_stop(ctx):
     _check(load_library().tn_server_stop(ctx))
 
 
+def tn_kernel_cgemm_scratch_bytes(M, N, K, nbatch=1, nb=1):
+    return load_library().tn_kernel_cgemm_scratch_bytes(M, N, K, nbatch, nb)
+
+
 def tn_kernel_cgemm(A, B, C, M, N, K, transA=0, transB=0, nbatch=1, nb=1, sAb=0, sBb=0,
-                    sCb=0, sAi=0, sBi=0, sCi=0, precision=TN_FP32_4M, stream=None):
-    """A, B, C: device pointers (ints), complex64 elements."""
+                    sCb=0, sAi=0, sBi=0, sCi=0, precision=TN_FP32_4M, scratch=None,
+                    scratch_bytes=0, stream=None):
+    """A, B, C, scratch: device pointers (ints), complex64 elements."""
     _check(load_library().tn_kernel_cgemm(A, B, C, M, N, K, transA, transB, nbatch, nb, sAb,
-                                          sBb, sCb, sAi, sBi, sCi, precision, stream))
+                                          sBb, sCb, sAi, sBi, sCi, precision, scratch,
+                                          scratch_bytes, stream))
 
 
 def tn_kernel_permute(src, dst, rank, perm, nb=1, stream=None):

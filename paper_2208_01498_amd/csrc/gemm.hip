@@ -1,0 +1,492 @@
+// Complex GEMM kernels of the pairwise steps (gfx950).
+//
+// C[m][n] = sum_k A(m,k) B(k,n) for every (bitstring b, batch-label value),
+// complex64 in HBM, FP32 accumulation.  Four families, chosen from the shape
+// only (never from the batch size, so a result is bitwise the same in any
+// chunk):
+//   k_cgemm<0,...>  FP32 4M on v_mfma_f32_32x32x2_f32: interleaved complex A
+//                   gives the real operand rows (Ar, Ai) directly and B is
+//                   expanded on the fly to [[Br Bi] [-Bi Br]], so one MFMA is
+//                   a 32 (m) x 16 (complex n) x 1 (complex k) product
+//   k_cgemm<2,...>  split bf16 on v_mfma_f32_32x32x16_bf16: operands are
+//                   split x = hi + lo when staged into LDS, and
+//                   hi*hi + hi*lo + lo*hi are accumulated in FP32; one MFMA is
+//                   32 x 16 x 8 (complex)
+//   k_cgemm_dot     tiny M*N with long K: a K-parallel dot product
+//   split-K         when a shape has too few output tiles to fill the chip,
+//                   K is cut into a fixed number of ranges whose partial
+//                   products are summed in range order by k_reduce_splitk
+// Tiles: 4 waves per workgroup; a wave owns WMF x WNF blocks of 32 x 16
+// (complex); KT = 16 complex k per stage; global loads of the next stage are
+// issued before the MFMAs of the current one and land in the other half of
+// a double-buffered LDS, one barrier per stage.
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+namespace {
+
+constexpr int KT = 16;
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+    hi = __float2bfloat16(x);
+    lo = __float2bfloat16(x - __bfloat162float(hi));
+}
+
+template <int PREC, int WGM, int WGN, int WMF, int WNF>
+struct Smem {
+    static constexpr int BM = WGM * 32 * WMF;
+    static constexpr int BN = WGN * 16 * WNF;
+    // FP32: A as [k][m], B as [k][n] (complex), padded rows
+    static constexpr int PA = BM + 2;
+    static constexpr int PB = BN + 2;
+    // bf16: A as [m][2*KT real], B as [2*BN real cols][2*KT real rows]
+    static constexpr int RA = 2 * KT + 8;
+    static constexpr size_t bytes_fp32 = 2 * (size_t)KT * (PA + PB) * sizeof(float2);
+    static constexpr size_t bytes_bf16 = 2 * (size_t)(2 * BM * RA + 2 * 2 * BN * RA) * 2;
+    static constexpr size_t bytes = PREC == 0 ? bytes_fp32 : bytes_bf16;
+};
+
+}  // namespace
+
+template <int PREC, int WGM, int WGN, int WMF, int WNF, bool TA, bool TB>
+__global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
+    using S = Smem<PREC, WGM, WGN, WMF, WNF>;
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int BM = S::BM, BN = S::BN, PA = S::PA, PB = S::PB, RA = S::RA;
+    constexpr int FA = BM * KT / 2;      // float4 (2 complex) loads per A tile
+    constexpr int FB = KT * BN / 2;
+    constexpr int LA = (FA + NT - 1) / NT;
+    constexpr int LB = (FB + NT - 1) / NT;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+
+    const int tiles_m = (g.M + BM - 1) / BM;
+    const int tiles_n = (g.N + BN - 1) / BN;
+    const size_t tiles = (size_t)tiles_m * tiles_n;
+    size_t blk = blockIdx.x;
+    const size_t tile = blk % tiles;
+    blk /= tiles;
+    const int split = (int)(blk % g.splits);
+    blk /= g.splits;
+    const size_t ib = blk % g.nbatch;
+    const size_t bb = blk / g.nbatch;
+    const int tm = (int)(tile % tiles_m);
+    const int tn = (int)(tile / tiles_m);
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int kper = g.K / g.splits;
+    const int kb = split * kper, ke = kb + kper;
+    const float2* A = g.A + bb * g.sAb + ib * g.sAi;
+    const float2* B = g.B + bb * g.sBb + ib * g.sBi;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = (wave % WGM) * (32 * WMF);
+    const int wn = (wave / WGM) * (16 * WNF);
+    const int half = lane >> 5;
+    const int l32 = lane & 31;
+
+    floatx16 acc[WMF][WNF];
+#pragma unroll
+    for (int i = 0; i < WMF; ++i)
+#pragma unroll
+        for (int j = 0; j < WNF; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    float4 ra[LA], rb[LB];
+    auto ldA = [&](int m, int k) -> float2 {
+        if (m0 + m >= g.M || k >= ke) return make_float2(0.f, 0.f);
+        return TA ? A[(size_t)k * g.M + m0 + m] : A[(size_t)(m0 + m) * g.K + k];
+    };
+    auto ldB = [&](int k, int n) -> float2 {
+        if (n0 + n >= g.N || k >= ke) return make_float2(0.f, 0.f);
+        return TB ? B[(size_t)(n0 + n) * g.K + k] : B[(size_t)k * g.N + n0 + n];
+    };
+    auto load = [&](int k0) {
+        const bool fullA = (m0 + BM <= g.M) && (k0 + KT <= ke);
+        const bool fullB = (n0 + BN <= g.N) && (k0 + KT <= ke);
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            const int f = tid + i * NT;
+            if (f >= FA) break;
+            if (!TA) {
+                const int m = f / (KT / 2), k = 2 * (f % (KT / 2));
+                if (fullA) ra[i] = *reinterpret_cast<const float4*>(A + (size_t)(m0 + m) * g.K + k0 + k);
+                else {
+                    float2 x = ldA(m, k0 + k), y = ldA(m, k0 + k + 1);
+                    ra[i] = make_float4(x.x, x.y, y.x, y.y);
+                }
+            } else {
+                const int k = f / (BM / 2), m = 2 * (f % (BM / 2));
+                if (fullA) ra[i] = *reinterpret_cast<const float4*>(A + (size_t)(k0 + k) * g.M + m0 + m);
+                else {
+                    float2 x = ldA(m, k0 + k), y = ldA(m + 1, k0 + k);
+                    ra[i] = make_float4(x.x, x.y, y.x, y.y);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < LB; ++i) {
+            const int f = tid + i * NT;
+            if (f >= FB) break;
+            if (!TB) {
+                const int k = f / (BN / 2), n = 2 * (f % (BN / 2));
+                if (fullB) rb[i] = *reinterpret_cast<const float4*>(B + (size_t)(k0 + k) * g.N + n0 + n);
+                else {
+                    float2 x = ldB(k0 + k, n), y = ldB(k0 + k, n + 1);
+                    rb[i] = make_float4(x.x, x.y, y.x, y.y);
+                }
+            } else {
+                const int n = f / (KT / 2), k = 2 * (f % (KT / 2));
+                if (fullB) rb[i] = *reinterpret_cast<const float4*>(B + (size_t)(n0 + n) * g.K + k0 + k);
+                else {
+                    float2 x = ldB(k0 + k, n), y = ldB(k0 + k + 1, n);
+                    rb[i] = make_float4(x.x, x.y, y.x, y.y);
+                }
+            }
+        }
+    };
+
+    // ---------------------------------------------------------------- FP32
+    float2* As = reinterpret_cast<float2*>(smem);              // [2][KT][PA]
+    float2* Bs = As + 2 * KT * PA;                              // [2][KT][PB]
+    // ---------------------------------------------------------------- bf16
+    __bf16* Ah = reinterpret_cast<__bf16*>(smem);               // [2][BM][RA]
+    __bf16* Al = Ah + 2 * BM * RA;
+    __bf16* Bh = Al + 2 * BM * RA;                               // [2][2BN][RA]
+    __bf16* Bl = Bh + 2 * 2 * BN * RA;
+
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            const int f = tid + i * NT;
+            if (f >= FA) break;
+            int m, k, m2, k2;   // element 0 at (m,k), element 1 at (m2,k2)
+            if (!TA) { m = f / (KT / 2); k = 2 * (f % (KT / 2)); m2 = m; k2 = k + 1; }
+            else { k = f / (BM / 2); m = 2 * (f % (BM / 2)); m2 = m + 1; k2 = k; }
+            const float2 x = make_float2(ra[i].x, ra[i].y), y = make_float2(ra[i].z, ra[i].w);
+            if constexpr (PREC == 0) {
+                float2* a = As + buf * KT * PA;
+                if (TA) *reinterpret_cast<float4*>(a + k * PA + m) = ra[i];
+                else { a[k * PA + m] = x; a[k2 * PA + m2] = y; }
+            } else {
+                __bf16* ah = Ah + buf * BM * RA;
+                __bf16* al = Al + buf * BM * RA;
+                __bf16 h, l;
+                split_bf16(x.x, h, l); ah[m * RA + 2 * k] = h; al[m * RA + 2 * k] = l;
+                split_bf16(x.y, h, l); ah[m * RA + 2 * k + 1] = h; al[m * RA + 2 * k + 1] = l;
+                split_bf16(y.x, h, l); ah[m2 * RA + 2 * k2] = h; al[m2 * RA + 2 * k2] = l;
+                split_bf16(y.y, h, l); ah[m2 * RA + 2 * k2 + 1] = h; al[m2 * RA + 2 * k2 + 1] = l;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < LB; ++i) {
+            const int f = tid + i * NT;
+            if (f >= FB) break;
+            int k, n, k2, n2;
+            if (!TB) { k = f / (BN / 2); n = 2 * (f % (BN / 2)); k2 = k; n2 = n + 1; }
+            else { n = f / (KT / 2); k = 2 * (f % (KT / 2)); n2 = n; k2 = k + 1; }
+            const float2 x = make_float2(rb[i].x, rb[i].y), y = make_float2(rb[i].z, rb[i].w);
+            if constexpr (PREC == 0) {
+                float2* b = Bs + buf * KT * PB;
+                if (!TB) *reinterpret_cast<float4*>(b + k * PB + n) = rb[i];
+                else { b[k * PB + n] = x; b[k2 * PB + n2] = y; }
+            } else {
+                __bf16* bh = Bh + buf * 2 * BN * RA;
+                __bf16* bl = Bl + buf * 2 * BN * RA;
+                auto put = [&](int kk, int nn, float2 v) {
+                    // real column 2n: rows (2k, 2k+1) = (Br, -Bi); column 2n+1: (Bi, Br)
+                    __bf16 h, l;
+                    split_bf16(v.x, h, l);
+                    bh[(2 * nn) * RA + 2 * kk] = h; bl[(2 * nn) * RA + 2 * kk] = l;
+                    bh[(2 * nn + 1) * RA + 2 * kk + 1] = h; bl[(2 * nn + 1) * RA + 2 * kk + 1] = l;
+                    split_bf16(-v.y, h, l);
+                    bh[(2 * nn) * RA + 2 * kk + 1] = h; bl[(2 * nn) * RA + 2 * kk + 1] = l;
+                    split_bf16(v.y, h, l);
+                    bh[(2 * nn + 1) * RA + 2 * kk] = h; bl[(2 * nn + 1) * RA + 2 * kk] = l;
+                };
+                put(k, n, x);
+                put(k2, n2, y);
+            }
+        }
+    };
+
+    auto compute = [&](int buf) {
+        if constexpr (PREC == 0) {
+            const float2* a = As + buf * KT * PA;
+            const float2* b = Bs + buf * KT * PB;
+#pragma unroll
+            for (int kk = 0; kk < KT; ++kk) {
+                float av[WMF], bv[WNF];
+#pragma unroll
+                for (int i = 0; i < WMF; ++i) {
+                    const float2 x = a[kk * PA + wm + i * 32 + l32];
+                    av[i] = half ? x.y : x.x;
+                }
+#pragma unroll
+                for (int j = 0; j < WNF; ++j) {
+                    const float2 y = b[kk * PB + wn + j * 16 + (l32 >> 1)];
+                    const int c = l32 & 1;
+                    bv[j] = half ? (c ? y.x : -y.y) : (c ? y.y : y.x);
+                }
+#pragma unroll
+                for (int i = 0; i < WMF; ++i)
+#pragma unroll
+                    for (int j = 0; j < WNF; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+            }
+        } else {
+            const __bf16* ah = Ah + buf * BM * RA;
+            const __bf16* al = Al + buf * BM * RA;
+            const __bf16* bh = Bh + buf * 2 * BN * RA;
+            const __bf16* bl = Bl + buf * 2 * BN * RA;
+#pragma unroll
+            for (int kc = 0; kc < KT / 8; ++kc) {
+                bf16x8 xh[WMF], xl[WMF], yh[WNF], yl[WNF];
+#pragma unroll
+                for (int i = 0; i < WMF; ++i) {
+                    const int m = wm + i * 32 + l32;
+                    xh[i] = *reinterpret_cast<const bf16x8*>(ah + m * RA + 16 * kc + 8 * half);
+                    xl[i] = *reinterpret_cast<const bf16x8*>(al + m * RA + 16 * kc + 8 * half);
+                }
+#pragma unroll
+                for (int j = 0; j < WNF; ++j) {
+                    const int col = 2 * (wn + j * 16) + l32;
+                    yh[j] = *reinterpret_cast<const bf16x8*>(bh + col * RA + 16 * kc + 8 * half);
+                    yl[j] = *reinterpret_cast<const bf16x8*>(bl + col * RA + 16 * kc + 8 * half);
+                }
+#pragma unroll
+                for (int i = 0; i < WMF; ++i)
+#pragma unroll
+                    for (int j = 0; j < WNF; ++j) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], yh[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yl[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yh[j], acc[i][j], 0, 0, 0);
+                    }
+            }
+        }
+    };
+
+    const int nk = (kper + KT - 1) / KT;
+    load(kb);
+    store(0);
+    __syncthreads();
+    for (int t = 0; t < nk; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < nk) load(kb + (t + 1) * KT);
+        compute(buf);
+        if (t + 1 < nk) store(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: acc[i][j][r] is real row 8*(r/4) + 4*half + r%4, column l32
+    float* out;
+    size_t ldm, ldn;
+    if (g.splits > 1) {
+        out = reinterpret_cast<float*>(g.P + (((size_t)split * g.nb + bb) * g.nbatch + ib) * (size_t)g.M * g.N);
+        ldm = g.N; ldn = 1;
+    } else {
+        out = reinterpret_cast<float*>(g.C + bb * g.sCb + ib * g.sCi);
+        if (g.transC) { ldm = 1; ldn = g.M; } else { ldm = g.N; ldn = 1; }
+    }
+#pragma unroll
+    for (int i = 0; i < WMF; ++i)
+#pragma unroll
+        for (int j = 0; j < WNF; ++j) {
+            const int n = n0 + wn + j * 16 + (l32 >> 1);
+            if (n >= g.N) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (m < g.M) out[2 * ((size_t)m * ldm + (size_t)n * ldn) + (l32 & 1)] = acc[i][j][r];
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Tiny outputs (M*N <= 16), any K: each workgroup sums one K range of one
+// batch entry; the 256 lanes are split into M*N groups of L = 256/(M*N)
+// consecutive lanes, one output per group, lanes striding along k, followed
+// by an LDS tree reduction within each group (fixed order).
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_cgemm_dot(GemmArgs g) {
+    __shared__ float2 red[256];
+    size_t blk = blockIdx.x;
+    const int split = (int)(blk % g.splits);
+    blk /= g.splits;
+    const size_t ib = blk % g.nbatch;
+    const size_t bb = blk / g.nbatch;
+    const int kper = g.K / g.splits;
+    const int kb = split * kper, ke = kb + kper;
+    const float2* A = g.A + bb * g.sAb + ib * g.sAi;
+    const float2* B = g.B + bb * g.sBb + ib * g.sBi;
+    const int M = g.M, N = g.N, MN = M * N;
+    const int L = 256 / MN;
+    const int tid = threadIdx.x;
+    const int o = tid / L, kl = tid % L;
+    const int m = o / N, n = o % N;
+    float cr = 0.f, ci = 0.f;
+    for (int k = kb + kl; k < ke; k += L) {
+        const float2 a = TA ? A[(size_t)k * M + m] : A[(size_t)m * g.K + k];
+        const float2 b = TB ? B[(size_t)n * g.K + k] : B[(size_t)k * N + n];
+        cr = fmaf(a.x, b.x, cr);
+        cr = fmaf(-a.y, b.y, cr);
+        ci = fmaf(a.x, b.y, ci);
+        ci = fmaf(a.y, b.x, ci);
+    }
+    red[tid] = make_float2(cr, ci);
+    __syncthreads();
+    for (int w = L / 2; w > 0; w >>= 1) {
+        if (kl < w) {
+            red[tid].x += red[tid + w].x;
+            red[tid].y += red[tid + w].y;
+        }
+        __syncthreads();
+    }
+    if (kl == 0) {
+        const float2 v = red[tid];
+        if (g.splits > 1) {
+            g.P[(((size_t)split * g.nb + bb) * g.nbatch + ib) * (size_t)MN + o] = v;
+        } else {
+            float2* C = g.C + bb * g.sCb + ib * g.sCi;
+            C[g.transC ? (size_t)n * M + m : (size_t)m * N + n] = v;
+        }
+    }
+}
+
+// Sum of split-K partials in range order, written in C's layout.
+__global__ void k_reduce_splitk(GemmArgs g) {
+    const size_t MN = (size_t)g.M * g.N;
+    const size_t per = MN * g.nbatch * g.nb;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < per;
+         e += (size_t)gridDim.x * blockDim.x) {
+        float2 s = g.P[e];
+        for (int sp = 1; sp < g.splits; ++sp) {
+            const float2 v = g.P[(size_t)sp * per + e];
+            s.x += v.x;
+            s.y += v.y;
+        }
+        const size_t mn = e % MN;
+        const size_t bi = e / MN;
+        const size_t ib = bi % g.nbatch, bb = bi / g.nbatch;
+        const size_t m = mn / g.N, n = mn % g.N;
+        g.C[bb * g.sCb + ib * g.sCi + (g.transC ? n * g.M + m : m * g.N + n)] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side dispatch
+
+static int ilog2(long long x) { int r = 0; while ((1ll << r) < x) ++r; return r; }
+
+GemmChoice choose_gemm(int M, int N, int K, int nbatch) {
+    GemmChoice c{};
+    c.swap = 0;
+    c.splits = 1;
+    long long tiles = 1;
+    if ((long long)M * N <= 16) {
+        c.kind = GEMM_DOT;
+        long long want = K / 2048;
+        c.splits = (int)std::max(1ll, std::min(1024ll, want));
+        return c;
+    }
+    int m = M, n = N;
+    if (N > M && !(M >= 64 && N >= 64)) { c.swap = 1; m = N; n = M; }
+    if (m >= 128 && n >= 128) { c.kind = GEMM_MFMA_128x128; tiles = (long long)(m / 128) * (n / 128); }
+    else if (m >= 64 && n >= 64) { c.kind = GEMM_MFMA_64x64; tiles = (long long)(m / 64) * (n / 64); }
+    else { c.kind = GEMM_MFMA_128x16; tiles = (long long)((m + 127) / 128) * ((n + 15) / 16); }
+    long long wgs = tiles * nbatch;
+    int s = 1;
+    while (wgs * s < 512 && (long long)K / (2 * s) >= 4 * KT && s < 64) s *= 2;
+    c.splits = s;
+    return c;
+}
+
+size_t gemm_scratch_elems(int M, int N, int K, int nbatch, int nb) {
+    GemmChoice c = choose_gemm(M, N, K, nbatch);
+    if (c.splits <= 1) return 0;
+    return (size_t)c.splits * nb * nbatch * (size_t)M * N;
+}
+
+template <int PREC, int WGM, int WGN, int WMF, int WNF, bool TA, bool TB>
+static void launch_one(const GemmArgs& g, size_t grid, hipStream_t s) {
+    using SM = Smem<PREC, WGM, WGN, WMF, WNF>;
+    const size_t lds = SM::bytes;
+    auto* fn = &k_cgemm<PREC, WGM, WGN, WMF, WNF, TA, TB>;
+    static bool attr = false;       // one per instantiation; a repeated call is harmless
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr = true;
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64 * WGM * WGN), lds, s, g);
+}
+
+template <int PREC, int WGM, int WGN, int WMF, int WNF>
+static void launch_cfg(const GemmArgs& g, size_t grid, hipStream_t s) {
+    if (g.transA) {
+        if (g.transB) launch_one<PREC, WGM, WGN, WMF, WNF, true, true>(g, grid, s);
+        else launch_one<PREC, WGM, WGN, WMF, WNF, true, false>(g, grid, s);
+    } else {
+        if (g.transB) launch_one<PREC, WGM, WGN, WMF, WNF, false, true>(g, grid, s);
+        else launch_one<PREC, WGM, WGN, WMF, WNF, false, false>(g, grid, s);
+    }
+}
+
+template <int WGM, int WGN, int WMF, int WNF>
+static void launch_prec(const GemmArgs& g, int precision, size_t grid, hipStream_t s) {
+    if (precision == 2) launch_cfg<2, WGM, WGN, WMF, WNF>(g, grid, s);
+    else launch_cfg<0, WGM, WGN, WMF, WNF>(g, grid, s);
+}
+
+hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
+    GemmChoice c = choose_gemm(g0.M, g0.N, g0.K, g0.nbatch);
+    GemmArgs g = g0;
+    if (c.swap) {
+        // C^T = B^T A^T, written transposed
+        g.A = g0.B; g.B = g0.A;
+        g.M = g0.N; g.N = g0.M;
+        g.transA = !g0.transB; g.transB = !g0.transA;
+        g.sAb = g0.sBb; g.sAi = g0.sBi; g.sBb = g0.sAb; g.sBi = g0.sAi;
+        g.transC = !g0.transC;
+    }
+    g.splits = c.splits;
+    if (c.splits > 1 && !g.P) return hipErrorInvalidValue;
+    const size_t batches = (size_t)g.nbatch * g.nb * c.splits;
+    if (c.kind == GEMM_DOT) {
+        if (g.transA) {
+            if (g.transB) hipLaunchKernelGGL((k_cgemm_dot<true, true>), dim3((unsigned)batches), dim3(256), 0, s, g);
+            else hipLaunchKernelGGL((k_cgemm_dot<true, false>), dim3((unsigned)batches), dim3(256), 0, s, g);
+        } else {
+            if (g.transB) hipLaunchKernelGGL((k_cgemm_dot<false, true>), dim3((unsigned)batches), dim3(256), 0, s, g);
+            else hipLaunchKernelGGL((k_cgemm_dot<false, false>), dim3((unsigned)batches), dim3(256), 0, s, g);
+        }
+    } else {
+        int bm = 128, bn = 128;
+        if (c.kind == GEMM_MFMA_64x64) { bm = 64; bn = 64; }
+        if (c.kind == GEMM_MFMA_128x16) { bm = 128; bn = 16; }
+        const size_t grid = (size_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * batches;
+        if (c.kind == GEMM_MFMA_128x128) launch_prec<2, 2, 2, 4>(g, precision, grid, s);
+        else if (c.kind == GEMM_MFMA_64x64) launch_prec<2, 2, 1, 2>(g, precision, grid, s);
+        else launch_prec<4, 1, 1, 1>(g, precision, grid, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || c.splits <= 1) return e;
+    const size_t per = (size_t)g.M * g.N * g.nbatch * g.nb;
+    unsigned blocks = (unsigned)std::min<size_t>((per + 255) / 256, 1u << 16);
+    hipLaunchKernelGGL(k_reduce_splitk, dim3(blocks), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+int gemm_kind(const GemmArgs& g, int precision) {
+    (void)precision;
+    return choose_gemm(g.M, g.N, g.K, g.nbatch).kind;
+}

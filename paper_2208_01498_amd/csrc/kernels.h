@@ -39,6 +39,9 @@ struct GemmArgs {
     const float2* A;
     const float2* B;
     float2* C;
+    float2* P;                // split-K partials (splits x nb x nbatch x M x N)
+    int splits;               // set by the dispatcher
+    int transC;               // C stored [N][M]
     int M, N, K;
     int transA, transB;       // A stored [K][M] / B stored [N][K]
     int nbatch;               // inner batch count (batch labels)
@@ -49,6 +52,15 @@ struct GemmArgs {
 
 hipError_t launch_gather(const GatherArgs& g, hipStream_t s);
 hipError_t launch_permute(const PermArgs& a, hipStream_t s);
+enum { GEMM_DOT = 0, GEMM_MFMA_64x64 = 1, GEMM_MFMA_128x128 = 2, GEMM_MFMA_128x16 = 3 };
+struct GemmChoice {
+    int kind;                 // GEMM_*
+    int splits;               // K ranges (1 = no split-K)
+    int swap;                 // compute C^T = B^T A^T
+};
+// Kernel choice from the shape only (not from the outer batch count).
+GemmChoice choose_gemm(int M, int N, int K, int nbatch);
+size_t gemm_scratch_elems(int M, int N, int K, int nbatch, int nb);
 hipError_t launch_gemm(const GemmArgs& g, int precision, hipStream_t s);
 int gemm_kind(const GemmArgs& g, int precision);
 hipError_t launch_zero_acc(double2* acc, int nb, hipStream_t s);

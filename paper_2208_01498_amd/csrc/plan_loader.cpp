@@ -13,6 +13,7 @@
 #include <numeric>
 #include <set>
 
+#include "kernels.h"
 #include "tn_internal.h"
 
 namespace tn {
@@ -359,6 +360,7 @@ MemPlan plan_memory(const PlanHost& p, int chunk) {
     mp.tensor_off.assign(T, kNone);
     mp.permA_off.assign(p.steps.size(), kNone);
     mp.permB_off.assign(p.steps.size(), kNone);
+    mp.scratch_off.assign(p.steps.size(), kNone);
     struct Buf { size_t bytes; int start, end; size_t* off; };
     std::vector<Buf> bufs;
     auto elems = [&](int rk, bool hb) { return (size_t(1) << rk) * (hb ? (size_t)chunk : 1); };
@@ -386,10 +388,28 @@ MemPlan plan_memory(const PlanHost& p, int chunk) {
         }
         bufs.push_back({elems(p.rank[t], p.has_b[t]) * 8, start, end, &mp.tensor_off[t]});
     }
+    // a permuted operand is re-permuted only when the operand itself changed,
+    // so its copy lives like the operand
+    auto operand_life = [&](int t, int s, int& start, int& end) {
+        const int q = s;
+        if (t < nL || period(p.steps[q].dep_mask) < period(p.dep[t])) { start = -1; end = INF; }
+        else { start = s; end = s; }
+    };
     for (size_t s = 0; s < p.steps.size(); ++s) {
         const Step& st = p.steps[s];
-        if (st.permA) bufs.push_back({elems((int)st.orderA.size(), st.hbA) * 8, (int)s, (int)s, &mp.permA_off[s]});
-        if (st.permB) bufs.push_back({elems((int)st.orderB.size(), st.hbB) * 8, (int)s, (int)s, &mp.permB_off[s]});
+        int a0, a1;
+        if (st.permA) {
+            operand_life(st.a, (int)s, a0, a1);
+            bufs.push_back({elems((int)st.orderA.size(), st.hbA) * 8, a0, a1, &mp.permA_off[s]});
+        }
+        if (st.permB) {
+            operand_life(st.b, (int)s, a0, a1);
+            bufs.push_back({elems((int)st.orderB.size(), st.hbB) * 8, a0, a1, &mp.permB_off[s]});
+        }
+        const int M = 1 << st.m_bits, N = 1 << st.n_bits, K = 1 << st.k_bits;
+        const int Mk = st.swapC ? N : M, Nk = st.swapC ? M : N;
+        size_t se = gemm_scratch_elems(Mk, Nk, K, 1 << st.batch_bits, st.hbC ? chunk : 1);
+        if (se) bufs.push_back({se * 8, (int)s, (int)s, &mp.scratch_off[s]});
     }
     for (auto& b : bufs) b.bytes = (b.bytes + 255) / 256 * 256;
     std::vector<int> idx(bufs.size());

@@ -176,7 +176,7 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                 if (rc0) return rc0;
                 HIPCHK(ctx, launch_gather(g, stream));
                 es.kernels_gather++;
-                return ev_end(4, 0.0, 8.0 * std::ldexp(1.0, g.n_mat) * g.nb);
+                return ev_end(5, 0.0, 8.0 * std::ldexp(1.0, g.n_mat) * g.nb);
             };
             if (p.steps.empty()) {
                 int rc = gather(0);
@@ -194,7 +194,11 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                 if (rc) return rc;
                 const float2* pa = tensor_ptr(st.a);
                 const float2* pb = tensor_ptr(st.b);
-                if (st.permA) {
+                const bool redoA = (s == 0) || (p.dep[st.a] & changed);
+                const bool redoB = (s == 0) || (p.dep[st.b] & changed);
+                if (st.permA && !redoA) pa = reinterpret_cast<float2*>(ws + mp.permA_off[si]);
+                if (st.permB && !redoB) pb = reinterpret_cast<float2*>(ws + mp.permB_off[si]);
+                if (st.permA && redoA) {
                     PermArgs a{};
                     fill_perm(a, st.permA_map, (int)st.orderA.size());
                     a.src = pa;
@@ -205,11 +209,11 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                     HIPCHK(ctx, launch_permute(a, stream));
                     es.kernels_permute++;
                     es.permute_bytes += 16.0 * std::ldexp(1.0, a.rank) * a.nb;
-                    rc = ev_end(3, 0.0, 16.0 * std::ldexp(1.0, a.rank) * a.nb);
+                    rc = ev_end(4, 0.0, 16.0 * std::ldexp(1.0, a.rank) * a.nb);
                     if (rc) return rc;
                     pa = a.dst;
                 }
-                if (st.permB) {
+                if (st.permB && redoB) {
                     PermArgs a{};
                     fill_perm(a, st.permB_map, (int)st.orderB.size());
                     a.src = pb;
@@ -220,7 +224,7 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                     HIPCHK(ctx, launch_permute(a, stream));
                     es.kernels_permute++;
                     es.permute_bytes += 16.0 * std::ldexp(1.0, a.rank) * a.nb;
-                    rc = ev_end(3, 0.0, 16.0 * std::ldexp(1.0, a.rank) * a.nb);
+                    rc = ev_end(4, 0.0, 16.0 * std::ldexp(1.0, a.rank) * a.nb);
                     if (rc) return rc;
                     pb = a.dst;
                 }
@@ -246,6 +250,8 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                 g.sCb = nbat * M * N; g.sCi = M * N;
                 g.nbatch = (int)nbat;
                 g.nb = nbC;
+                if (mp.scratch_off[si] != std::numeric_limits<size_t>::max())
+                    g.P = reinterpret_cast<float2*>(ws + mp.scratch_off[si]);
                 rc = ev_begin();
                 if (rc) return rc;
                 HIPCHK(ctx, launch_gemm(g, precision, stream));
@@ -424,12 +430,25 @@ int tn_contract_amplitudes(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bit
     return rc;
 }
 
+static bool pow2(long long x) { return x > 0 && (x & (x - 1)) == 0; }
+
+size_t tn_kernel_cgemm_scratch_bytes(int32_t M, int32_t N, int32_t K, int32_t nbatch, int32_t nb) {
+    if (!pow2(M) || !pow2(N) || !pow2(K) || nbatch <= 0 || nb <= 0) return 0;
+    return gemm_scratch_elems(M, N, K, nbatch, nb) * 8;
+}
+
 int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N, int32_t K,
                     int32_t transA, int32_t transB, int32_t nbatch, int32_t nb,
                     int64_t sAb, int64_t sBb, int64_t sCb, int64_t sAi, int64_t sBi,
-                    int64_t sCi, int32_t precision, void* hip_stream) {
-    if (!A || !B || !C || M <= 0 || N <= 0 || K <= 0 || nbatch <= 0 || nb <= 0) {
-        set_error("bad gemm arguments");
+                    int64_t sCi, int32_t precision, void* scratch, size_t scratch_bytes,
+                    void* hip_stream) {
+    if (!A || !B || !C || !pow2(M) || !pow2(N) || !pow2(K) || nbatch <= 0 || nb <= 0) {
+        set_error("bad gemm arguments (M, N, K must be powers of two)");
+        return TN_EINVAL;
+    }
+    const size_t need = gemm_scratch_elems(M, N, K, nbatch, nb) * 8;
+    if (need > scratch_bytes || (need && !scratch)) {
+        set_error("gemm needs " + std::to_string(need) + " bytes of scratch");
         return TN_EINVAL;
     }
     if (precision != TN_FP32_4M && precision != TN_SPLIT_BF16) { set_error("precision mode not available"); return TN_EINVAL; }
@@ -441,6 +460,7 @@ int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N,
     g.transA = transA ? 1 : 0; g.transB = transB ? 1 : 0;
     g.nbatch = nbatch; g.nb = nb;
     g.sAb = sAb; g.sBb = sBb; g.sCb = sCb; g.sAi = sAi; g.sBi = sBi; g.sCi = sCi;
+    g.P = static_cast<float2*>(scratch);
     tn_ctx* none = nullptr;
     HIPCHK(none, launch_gemm(g, precision, static_cast<hipStream_t>(hip_stream)));
     return TN_OK;

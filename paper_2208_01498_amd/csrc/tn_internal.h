@@ -99,6 +99,7 @@ struct MemPlan {
     size_t bytes = 0;                           // total workspace bytes
     std::vector<size_t> tensor_off;             // per tensor id (bytes), SIZE_MAX if none
     std::vector<size_t> permA_off, permB_off;   // per step, SIZE_MAX if none
+    std::vector<size_t> scratch_off;            // per step split-K partials, SIZE_MAX if none
     size_t acc_off = 0;                         // FP64 accumulators
     size_t bits_off = 0;                        // bitstrings
     size_t maps_off = 0;                        // per-step tables (none yet)

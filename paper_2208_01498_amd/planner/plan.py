@@ -102,7 +102,7 @@ class Plan:
 
 
 def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
-              n_circles=24, trials=1):
+              n_circles=24, trials=1, objective="time"):
     """Build a plan.  ``n_slices``: number of sliced labels (log2 of the slice
     count), or None to slice until the widest per-slice intermediate is at
     most ``target_width`` (log2 elements, batch included)."""
@@ -119,17 +119,22 @@ def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
     steps = best[1]
     sliced = []
     total = None
+    predicted = None
+    sm = SliceModel(net, steps, B=B, objective=objective) if steps else None
     if steps and (n_slices or target_width is not None):
-        sm = SliceModel(net, steps, B=B)
-        sliced, total, width = sm.greedy(n_slices=n_slices if n_slices else None,
-                                         target_width=target_width)
+        sliced, _, width = sm.greedy(n_slices=n_slices if n_slices else None,
+                                     target_width=target_width)
+    if sm is not None:
+        predicted, _ = sm.evaluate(sliced, ordered=True)
+        total = sm.last_flops
     lay = Layout(net, steps, sliced)
     leaf_order, step_layout = lay.run()
     st = plan_stats(net, steps, sliced=sliced, B=1)
     if total is None:
         total = st["flops"] * (1 << len(sliced))
     stats = dict(flops_per_b=st["flops"], max_bits=st["max_bits"],
-                 total_flops_per_b=total / B if sliced else st["flops"],
+                 total_flops_per_b=(total / B) if total else st["flops"],
+                 predicted=predicted,
                  permute_elems=lay.permute_elems, n_leaves=len(net.factors),
                  n_steps=len(steps))
     return Plan(circ, net, steps, sliced, leaf_order, step_layout, stats,

@@ -14,10 +14,13 @@ import math
 
 
 class SliceModel:
-    def __init__(self, net, steps, B=1):
+    def __init__(self, net, steps, B=1, peak_flops=157.3e12 * 0.6, peak_bw=8.0e12 * 0.6,
+                 launch=4e-6, objective="time"):
         self.net = net
         self.steps = steps
         self.B = B
+        self.peak_flops, self.peak_bw, self.launch = peak_flops, peak_bw, launch
+        self.objective = objective
         self.is_out = {l: lab.kind == "out" for l, lab in net.labels.items()}
         self.bits = {l: math.log2(lab.dim) for l, lab in net.labels.items()}
         nf = len(net.factors)
@@ -48,7 +51,8 @@ class SliceModel:
             ha, hbb = hb.pop(a), hb.pop(b)
             hc = ha or hbb
             st = sub.pop(a) | sub.pop(b)
-            self.rec.append((frozenset(u), frozenset(lc), frozenset(st), hc))
+            self.rec.append((frozenset(u), frozenset(lc), frozenset(st), hc,
+                             frozenset(la), frozenset(lb), ha, hbb))
             live[nid] = lc
             hb[nid] = hc
             sub[nid] = st
@@ -58,7 +62,8 @@ class SliceModel:
         wmax = max((sum(self.bits[l] for l in r[1]) for r in self.rec), default=0)
         umax = max((sum(self.bits[l] for l in r[0]) for r in self.rec), default=0)
         cand = set()
-        for u, lc, st, hc in self.rec:
+        for r in self.rec:
+            u, lc = r[0], r[1]
             if sum(self.bits[l] for l in lc) >= wmax - 6 or sum(self.bits[l] for l in u) >= umax - 3:
                 cand |= set(lc) | set(u)
         self.candidates = sorted(cand)
@@ -71,7 +76,8 @@ class SliceModel:
         Labels whose dependent steps cost least get the low bits."""
         S = list(sliced)
         dep = {l: 0.0 for l in S}
-        for u, lc, st, hc in self.rec:
+        for r in self.rec:
+            u, lc, st, hc = r[:4]
             hit = st & set(S)
             if hit:
                 ub = sum(self.bits[x] for x in u if x not in set(S))
@@ -89,13 +95,23 @@ class SliceModel:
         nS = len(S)
         total = 0.0
         width = 0.0
-        for u, lc, st, hc in self.rec:
+        self.last_flops = 0.0
+        for u, lc, st, hc, la, lb, ha, hb in self.rec:
             bsz = self.B if hc else 1
             hit = [pos[l] for l in st if l in Sset]
             ub = sum(self.bits[l] for l in u if l not in Sset)
             cb = sum(self.bits[l] for l in lc if l not in Sset)
-            c = 8.0 * 2.0 ** ub * bsz
-            total += c * (2.0 ** (nS - min(hit)) if hit else 1.0)
+            f = 8.0 * 2.0 ** ub * bsz
+            reps = 2.0 ** (nS - min(hit)) if hit else 1.0
+            self.last_flops += f * reps
+            if self.objective == "time":
+                ab = sum(self.bits[l] for l in la if l not in Sset)
+                bbits = sum(self.bits[l] for l in lb if l not in Sset)
+                byt = 8.0 * (2.0 ** ab * (self.B if ha else 1) + 2.0 ** bbits * (self.B if hb else 1)
+                             + 2.0 ** cb * bsz)
+                total += reps * (max(f / self.peak_flops, byt / self.peak_bw) + self.launch)
+            else:
+                total += f * reps
             width = max(width, cb + math.log2(bsz))
         return total, width
 

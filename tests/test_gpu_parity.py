@@ -103,8 +103,10 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
-GEMM_SHAPES = [(1, 1, 1), (4, 2, 1), (32, 16, 8), (64, 64, 8), (128, 128, 8), (256, 128, 64),
-               (128, 256, 16), (64, 32, 2), (512, 64, 128), (1024, 1024, 32)]
+GEMM_SHAPES = [(1, 1, 1), (4, 2, 1), (2, 2, 1 << 16), (1, 1, 1 << 14), (32, 16, 8), (64, 64, 8),
+               (128, 128, 8), (256, 128, 64), (128, 256, 16), (64, 32, 2), (512, 64, 128),
+               (1024, 1024, 32), (1024, 4, 4096), (4, 512, 2048), (16, 8, 256), (256, 256, 4096),
+               (128, 2, 1)]
 
 
 @pytest.mark.parametrize("M,N,K", GEMM_SHAPES)
@@ -121,10 +123,12 @@ def test_kernel_cgemm(M, N, K, tA, tB, prec):
     Bs = np.swapaxes(Bm, -1, -2).copy() if tB else Bm
     dA, dB = _dev(As.view(np.float32)), _dev(Bs.view(np.float32))
     dC = torch.zeros(nb * nbatch * M * N * 2, dtype=torch.float32, device="cuda")
-    print("case gemm", M, N, K, tA, tB, prec, flush=True)
+    sb = B.tn_kernel_cgemm_scratch_bytes(M, N, K, nbatch, nb)
+    scratch = torch.empty(max(sb, 8), dtype=torch.uint8, device="cuda")
+    print("case gemm", M, N, K, tA, tB, prec, "scratch", sb, flush=True)
     B.tn_kernel_cgemm(dA.data_ptr(), dB.data_ptr(), dC.data_ptr(), M, N, K, tA, tB, nbatch, nb,
                       sAb=nbatch * M * K, sBb=0, sCb=nbatch * M * N, sAi=M * K, sBi=K * N,
-                      sCi=M * N, precision=prec)
+                      sCi=M * N, precision=prec, scratch=scratch.data_ptr(), scratch_bytes=sb)
     torch.cuda.synchronize()
     C = dC.cpu().numpy().view(np.complex64).reshape(nb, nbatch, M, N)
     ref = np.matmul(A.astype(np.complex128), Bm.astype(np.complex128)[None])
