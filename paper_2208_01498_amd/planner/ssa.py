@@ -171,9 +171,12 @@ def ssa_candidates(pts, radii, rng, n_circles=24):
         coef = rng.standard_normal((d + 1, d))
         coef /= np.linalg.norm(coef, axis=1, keepdims=True)
         on = coef @ basis                                    # points of S^d with u.y = 0
-        back = _dilate(on, 1.0 / a) @ R                       # step 6: D^{-1}, then R^T
-        back = np.clip(back, -1, 1 - 1e-12)
-        Q = stereo_inv(back) * sc + mu
+        with np.errstate(divide="ignore", invalid="ignore"):
+            back = _dilate(on, 1.0 / a) @ R                   # step 6: D^{-1}, then R^T
+            back = np.clip(back, -1, 1 - 1e-12)
+            Q = stereo_inv(back) * sc + mu
+        if not np.all(np.isfinite(Q)):
+            continue                                         # circle through the pole
         seps.append(_fit_sphere(Q))
     return seps
 
