@@ -147,9 +147,10 @@ def main():
         "config": {"workload": "%s: %s" % (args.config, info["desc"]), "batch": nb,
                    "slices": 1 << len(plan.sliced), "precision": args.precision,
                    "chunk": st["chunk"], "n_chunks": st["n_chunks"],
-                   "plan_flops_per_amplitude": pinfo["flops_total_per_b"]},
+                   "slice_block": st["slice_block"],
+                   "algorithmic_flops_per_amplitude": st["algorithmic_flops"] / nb},
         "roofline": roofline,
-        "achieved_plan_tflops": pinfo["flops_total_per_b"] * nb * args.steps / el / 1e12,
+        "achieved_algorithmic_tflops": st["algorithmic_flops"] * args.steps / el / 1e12,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

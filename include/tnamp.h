@@ -63,7 +63,8 @@ typedef struct tn_plan_info_t {
     int32_t max_rank;                 /* widest intermediate, labels (batch excl.) */
     int32_t reserved;
     double flops_per_slice_per_b;     /* algorithmic real flops, 8 per complex MAC */
-    double flops_total_per_b;         /* over all slices, with slice reuse       */
+    double flops_total_per_b;         /* over all slices: each step once per value
+                                         of the sliced labels it depends on     */
     uint64_t peak_bytes_fixed;        /* workspace independent of the batch size */
     uint64_t peak_bytes_per_b;        /* plus this much per bitstring in a chunk */
 } tn_plan_info_t;
@@ -155,6 +156,8 @@ typedef struct tn_exec_stats {
     int64_t steps_reused;
     int32_t chunk;                    /* bitstrings per device chunk */
     int32_t n_chunks;
+    int32_t slice_block;              /* slices computed together per pass */
+    int32_t reserved;
     double algorithmic_flops;         /* sum over executed steps     */
     double permute_bytes;             /* 16 bytes per permuted element */
     /* per kernel class (0 dot-product GEMM for tiny outputs, 1 MFMA GEMM
@@ -172,6 +175,13 @@ typedef struct tn_exec_stats {
 
 /* Turn per-launch event timing of tn_contract_amplitudes on (1) or off (0). */
 int tn_ctx_set_profiling(tn_ctx* ctx, int32_t on);
+
+/* Slices computed together per pass of the slice loop, as log2 (-1 =
+ * automatic: the largest block that fits the workspace).  Tensors that depend
+ * on the low slice bits then hold one copy per slice of the block, and the
+ * slices of a block run as one batched (or folded) GEMM per step; every
+ * slice's arithmetic is unchanged, so results do not depend on the block. */
+int tn_ctx_set_slice_block(tn_ctx* ctx, int32_t log2_block);
 int tn_last_exec_stats(tn_ctx* ctx, tn_exec_stats* out);
 
 /*

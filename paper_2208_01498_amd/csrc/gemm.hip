@@ -35,6 +35,15 @@ namespace {
 
 constexpr int KT = 16;
 
+// bits of x at the set positions of m, compacted (parallel bit extract)
+__device__ __forceinline__ size_t pext_u(size_t x, unsigned m) {
+    size_t r = 0;
+    int k = 0;
+    for (; m; m &= m - 1, ++k)
+        if (x & (m & (~m + 1))) r |= size_t(1) << k;
+    return r;
+}
+
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
     hi = __float2bfloat16(x);
     lo = __float2bfloat16(x - __bfloat162float(hi));
@@ -67,8 +76,13 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
     constexpr int LB = (FB + NT - 1) / NT;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
-    const int tiles_m = (g.M + BM - 1) / BM;
-    const int tiles_n = (g.N + BN - 1) / BN;
+    // slice-block folding: Mt = M * nr (fold 2) or Nt = N * nr (fold 1); the
+    // folded index m' = r * M + m selects operand and output block r
+    const int Mt = g.fold == 2 ? g.M * g.nr : g.M;
+    const int Nt = g.fold == 1 ? g.N * g.nr : g.N;
+    const int lgM = __builtin_ctz((unsigned)g.M), lgN = __builtin_ctz((unsigned)g.N);
+    const int tiles_m = (Mt + BM - 1) / BM;
+    const int tiles_n = (Nt + BN - 1) / BN;
     const size_t tiles = (size_t)tiles_m * tiles_n;
     size_t blk = blockIdx.x;
     const size_t tile = blk % tiles;
@@ -76,14 +90,20 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
     const int split = (int)(blk % g.splits);
     blk /= g.splits;
     const size_t ib = blk % g.nbatch;
-    const size_t bb = blk / g.nbatch;
+    blk /= g.nbatch;
+    const size_t bb = blk % g.nb;
+    const size_t rr = g.fold == 0 ? blk / g.nb : 0;
+    const size_t outer = g.fold == 0 ? rr * g.nb + bb : bb;
+    const size_t n_outer = g.fold == 0 ? (size_t)g.nr * g.nb : (size_t)g.nb;
     const int tm = (int)(tile % tiles_m);
     const int tn = (int)(tile / tiles_m);
     const int m0 = tm * BM, n0 = tn * BN;
     const int kper = g.K / g.splits;
     const int kb = split * kper, ke = kb + kper;
-    const float2* A = g.A + bb * g.sAb + ib * g.sAi;
-    const float2* B = g.B + bb * g.sBb + ib * g.sBi;
+    const float2* A = g.A + bb * g.sAb + ib * g.sAi + pext_u(rr, g.mA) * g.sAr;
+    const float2* B = g.B + bb * g.sBb + ib * g.sBi + pext_u(rr, g.mB) * g.sBr;
+    const long long sAf = g.fold == 2 ? g.sAr : 0;    // per folded block
+    const long long sBf = g.fold == 1 ? g.sBr : 0;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -102,31 +122,41 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
     float4 ra[LA], rb[LB];
+    // address of A(m', k) / B(k, n') for folded indices
+    auto adA = [&](int mp, int k) -> size_t {
+        const int m = mp & (g.M - 1);
+        return (size_t)(mp >> lgM) * sAf + (TA ? (size_t)k * g.M + m : (size_t)m * g.K + k);
+    };
+    auto adB = [&](int k, int np) -> size_t {
+        const int n = np & (g.N - 1);
+        return (size_t)(np >> lgN) * sBf + (TB ? (size_t)n * g.K + k : (size_t)k * g.N + n);
+    };
     auto ldA = [&](int m, int k) -> float2 {
-        if (m0 + m >= g.M || k >= ke) return make_float2(0.f, 0.f);
-        return TA ? A[(size_t)k * g.M + m0 + m] : A[(size_t)(m0 + m) * g.K + k];
+        if (m0 + m >= Mt || k >= ke) return make_float2(0.f, 0.f);
+        return A[adA(m0 + m, k)];
     };
     auto ldB = [&](int k, int n) -> float2 {
-        if (n0 + n >= g.N || k >= ke) return make_float2(0.f, 0.f);
-        return TB ? B[(size_t)(n0 + n) * g.K + k] : B[(size_t)k * g.N + n0 + n];
+        if (n0 + n >= Nt || k >= ke) return make_float2(0.f, 0.f);
+        return B[adB(k, n0 + n)];
     };
     auto load = [&](int k0) {
-        const bool fullA = (m0 + BM <= g.M) && (k0 + KT <= ke);
-        const bool fullB = (n0 + BN <= g.N) && (k0 + KT <= ke);
+        // vector loads need the element pair inside one folded block
+        const bool fullA = (m0 + BM <= Mt) && (k0 + KT <= ke) && (!TA || g.M >= 2);
+        const bool fullB = (n0 + BN <= Nt) && (k0 + KT <= ke) && (TB || g.N >= 2);
 #pragma unroll
         for (int i = 0; i < LA; ++i) {
             const int f = tid + i * NT;
             if (f >= FA) break;
             if (!TA) {
                 const int m = f / (KT / 2), k = 2 * (f % (KT / 2));
-                if (fullA) ra[i] = *reinterpret_cast<const float4*>(A + (size_t)(m0 + m) * g.K + k0 + k);
+                if (fullA) ra[i] = *reinterpret_cast<const float4*>(A + adA(m0 + m, k0 + k));
                 else {
                     float2 x = ldA(m, k0 + k), y = ldA(m, k0 + k + 1);
                     ra[i] = make_float4(x.x, x.y, y.x, y.y);
                 }
             } else {
                 const int k = f / (BM / 2), m = 2 * (f % (BM / 2));
-                if (fullA) ra[i] = *reinterpret_cast<const float4*>(A + (size_t)(k0 + k) * g.M + m0 + m);
+                if (fullA) ra[i] = *reinterpret_cast<const float4*>(A + adA(m0 + m, k0 + k));
                 else {
                     float2 x = ldA(m, k0 + k), y = ldA(m + 1, k0 + k);
                     ra[i] = make_float4(x.x, x.y, y.x, y.y);
@@ -139,14 +169,14 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
             if (f >= FB) break;
             if (!TB) {
                 const int k = f / (BN / 2), n = 2 * (f % (BN / 2));
-                if (fullB) rb[i] = *reinterpret_cast<const float4*>(B + (size_t)(k0 + k) * g.N + n0 + n);
+                if (fullB) rb[i] = *reinterpret_cast<const float4*>(B + adB(k0 + k, n0 + n));
                 else {
                     float2 x = ldB(k0 + k, n), y = ldB(k0 + k, n + 1);
                     rb[i] = make_float4(x.x, x.y, y.x, y.y);
                 }
             } else {
                 const int n = f / (KT / 2), k = 2 * (f % (KT / 2));
-                if (fullB) rb[i] = *reinterpret_cast<const float4*>(B + (size_t)(n0 + n) * g.K + k0 + k);
+                if (fullB) rb[i] = *reinterpret_cast<const float4*>(B + adB(k0 + k, n0 + n));
                 else {
                     float2 x = ldB(k0 + k, n), y = ldB(k0 + k + 1, n);
                     rb[i] = make_float4(x.x, x.y, y.x, y.y);
@@ -288,25 +318,29 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
     }
 
     // epilogue: acc[i][j][r] is real row 8*(r/4) + 4*half + r%4, column l32
-    float* out;
-    size_t ldm, ldn;
-    if (g.splits > 1) {
-        out = reinterpret_cast<float*>(g.P + (((size_t)split * g.nb + bb) * g.nbatch + ib) * (size_t)g.M * g.N);
-        ldm = g.N; ldn = 1;
-    } else {
-        out = reinterpret_cast<float*>(g.C + bb * g.sCb + ib * g.sCi);
-        if (g.transC) { ldm = 1; ldn = g.M; } else { ldm = g.N; ldn = 1; }
-    }
+    const bool part = g.splits > 1;
+    float2* Cb = part ? g.P + (((size_t)split * n_outer + outer) * g.nbatch + ib) * (size_t)Mt * Nt
+                      : g.C + bb * g.sCb + ib * g.sCi + rr * g.sCr;
+    const long long sCm = g.fold == 2 ? g.sCr : 0, sCn = g.fold == 1 ? g.sCr : 0;
 #pragma unroll
     for (int i = 0; i < WMF; ++i)
 #pragma unroll
         for (int j = 0; j < WNF; ++j) {
-            const int n = n0 + wn + j * 16 + (l32 >> 1);
-            if (n >= g.N) continue;
+            const int np = n0 + wn + j * 16 + (l32 >> 1);
+            if (np >= Nt) continue;
+            const int n = np & (g.N - 1);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int m = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                if (m < g.M) out[2 * ((size_t)m * ldm + (size_t)n * ldn) + (l32 & 1)] = acc[i][j][r];
+                const int mp = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (mp >= Mt) continue;
+                size_t e;
+                if (part) e = (size_t)mp * Nt + np;
+                else {
+                    const int m = mp & (g.M - 1);
+                    e = (size_t)(mp >> lgM) * sCm + (size_t)(np >> lgN) * sCn +
+                        (g.transC ? (size_t)n * g.M + m : (size_t)m * g.N + n);
+                }
+                reinterpret_cast<float*>(Cb + e)[l32 & 1] = acc[i][j][r];
             }
         }
 }
@@ -323,11 +357,15 @@ __global__ void __launch_bounds__(256) k_cgemm_dot(GemmArgs g) {
     const int split = (int)(blk % g.splits);
     blk /= g.splits;
     const size_t ib = blk % g.nbatch;
-    const size_t bb = blk / g.nbatch;
+    blk /= g.nbatch;
+    const size_t bb = blk % g.nb;
+    const size_t rr = blk / g.nb;                    // slice block as an outer batch
+    const size_t outer = rr * g.nb + bb;
+    const size_t n_outer = (size_t)g.nr * g.nb;
     const int kper = g.K / g.splits;
     const int kb = split * kper, ke = kb + kper;
-    const float2* A = g.A + bb * g.sAb + ib * g.sAi;
-    const float2* B = g.B + bb * g.sBb + ib * g.sBi;
+    const float2* A = g.A + bb * g.sAb + ib * g.sAi + pext_u(rr, g.mA) * g.sAr;
+    const float2* B = g.B + bb * g.sBb + ib * g.sBi + pext_u(rr, g.mB) * g.sBr;
     const int M = g.M, N = g.N, MN = M * N;
     const int L = 256 / MN;
     const int tid = threadIdx.x;
@@ -354,18 +392,24 @@ __global__ void __launch_bounds__(256) k_cgemm_dot(GemmArgs g) {
     if (kl == 0) {
         const float2 v = red[tid];
         if (g.splits > 1) {
-            g.P[(((size_t)split * g.nb + bb) * g.nbatch + ib) * (size_t)MN + o] = v;
+            g.P[(((size_t)split * n_outer + outer) * g.nbatch + ib) * (size_t)MN + o] = v;
         } else {
-            float2* C = g.C + bb * g.sCb + ib * g.sCi;
+            float2* C = g.C + bb * g.sCb + ib * g.sCi + rr * g.sCr;
             C[g.transC ? (size_t)n * M + m : (size_t)m * N + n] = v;
         }
     }
 }
 
-// Sum of split-K partials in range order, written in C's layout.
+// Sum of split-K partials in range order, written in C's layout.  Partial
+// layout: [split][outer][inner batch][m'][n'] over the folded sizes.
 __global__ void k_reduce_splitk(GemmArgs g) {
-    const size_t MN = (size_t)g.M * g.N;
-    const size_t per = MN * g.nbatch * g.nb;
+    const int Mt = g.fold == 2 ? g.M * g.nr : g.M;
+    const int Nt = g.fold == 1 ? g.N * g.nr : g.N;
+    const int lgM = __builtin_ctz((unsigned)g.M), lgN = __builtin_ctz((unsigned)g.N);
+    const size_t n_outer = g.fold == 0 ? (size_t)g.nr * g.nb : (size_t)g.nb;
+    const size_t MN = (size_t)Mt * Nt;
+    const size_t per = MN * g.nbatch * n_outer;
+    const long long sCm = g.fold == 2 ? g.sCr : 0, sCn = g.fold == 1 ? g.sCr : 0;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < per;
          e += (size_t)gridDim.x * blockDim.x) {
         float2 s = g.P[e];
@@ -376,9 +420,14 @@ __global__ void k_reduce_splitk(GemmArgs g) {
         }
         const size_t mn = e % MN;
         const size_t bi = e / MN;
-        const size_t ib = bi % g.nbatch, bb = bi / g.nbatch;
-        const size_t m = mn / g.N, n = mn % g.N;
-        g.C[bb * g.sCb + ib * g.sCi + (g.transC ? n * g.M + m : m * g.N + n)] = s;
+        const size_t ib = bi % g.nbatch, outer = bi / g.nbatch;
+        const size_t bb = outer % g.nb, rr = g.fold == 0 ? outer / g.nb : 0;
+        const int mp = (int)(mn / Nt), np = (int)(mn % Nt);
+        const int m = mp & (g.M - 1), n = np & (g.N - 1);
+        const size_t c = bb * g.sCb + ib * g.sCi + rr * g.sCr + (size_t)(mp >> lgM) * sCm +
+                         (size_t)(np >> lgN) * sCn +
+                         (g.transC ? (size_t)n * g.M + m : (size_t)m * g.N + n);
+        g.C[c] = s;
     }
 }
 
@@ -387,33 +436,47 @@ __global__ void k_reduce_splitk(GemmArgs g) {
 
 static int ilog2(long long x) { int r = 0; while ((1ll << r) < x) ++r; return r; }
 
-GemmChoice choose_gemm(int M, int N, int K, int nbatch) {
+GemmChoice choose_gemm(int M, int N, int K, int nbatch, int Mt, int Nt) {
     GemmChoice c{};
     c.swap = 0;
     c.splits = 1;
-    long long tiles = 1;
+    if (Mt <= 0) Mt = M;
+    if (Nt <= 0) Nt = N;
     if ((long long)M * N <= 16) {
         c.kind = GEMM_DOT;
         long long want = K / 2048;
         c.splits = (int)std::max(1ll, std::min(1024ll, want));
         return c;
     }
-    int m = M, n = N;
-    if (N > M && !(M >= 64 && N >= 64)) { c.swap = 1; m = N; n = M; }
-    if (m >= 128 && n >= 128) { c.kind = GEMM_MFMA_128x128; tiles = (long long)(m / 128) * (n / 128); }
-    else if (m >= 64 && n >= 64) { c.kind = GEMM_MFMA_64x64; tiles = (long long)(m / 64) * (n / 64); }
-    else { c.kind = GEMM_MFMA_128x16; tiles = (long long)((m + 127) / 128) * ((n + 15) / 16); }
-    long long wgs = tiles * nbatch;
-    int s = 1;
-    while (wgs * s < 512 && (long long)K / (2 * s) >= 4 * KT && s < 64) s *= 2;
-    c.splits = s;
+    // K split from the unfolded shape only
+    {
+        int m = M, n = N;
+        if (n > m && !(m >= 64 && n >= 64)) std::swap(m, n);
+        long long tiles;
+        if (m >= 128 && n >= 128) tiles = (long long)(m / 128) * (n / 128);
+        else if (m >= 64 && n >= 64) tiles = (long long)(m / 64) * (n / 64);
+        else tiles = (long long)((m + 127) / 128) * ((n + 15) / 16);
+        long long wgs = tiles * nbatch;
+        int s = 1;
+        while (wgs * s < 512 && (long long)K / (2 * s) >= 4 * KT && s < 64) s *= 2;
+        c.splits = s;
+    }
+    // operand roles from the unfolded shape too: computing C^T = B^T A^T sums
+    // the two real products of an imaginary part in the other order, so the
+    // choice must not depend on the slice block
+    c.swap = (N > M && !(M >= 64 && N >= 64)) ? 1 : 0;
+    // tile shape from the folded sizes (does not change any summation)
+    int m = c.swap ? Nt : Mt, n = c.swap ? Mt : Nt;
+    if (m >= 128 && n >= 128) c.kind = GEMM_MFMA_128x128;
+    else if (m >= 64 && n >= 64) c.kind = GEMM_MFMA_64x64;
+    else c.kind = GEMM_MFMA_128x16;
     return c;
 }
 
-size_t gemm_scratch_elems(int M, int N, int K, int nbatch, int nb) {
+size_t gemm_scratch_elems(int M, int N, int K, int nbatch, int nouter) {
     GemmChoice c = choose_gemm(M, N, K, nbatch);
     if (c.splits <= 1) return 0;
-    return (size_t)c.splits * nb * nbatch * (size_t)M * N;
+    return (size_t)c.splits * nouter * nbatch * (size_t)M * N;
 }
 
 template <int PREC, int WGM, int WGN, int WMF, int WNF, bool TA, bool TB>
@@ -448,19 +511,34 @@ static void launch_prec(const GemmArgs& g, int precision, size_t grid, hipStream
 }
 
 hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
-    GemmChoice c = choose_gemm(g0.M, g0.N, g0.K, g0.nbatch);
     GemmArgs g = g0;
+    if (g.nr < 1) g.nr = 1;
+    if (g.nr == 1) g.fold = 0;
+    const int Mt0 = g.fold == 2 ? g.M * g.nr : g.M;
+    const int Nt0 = g.fold == 1 ? g.N * g.nr : g.N;
+    GemmChoice c = choose_gemm(g.M, g.N, g.K, g.nbatch, Mt0, Nt0);
+    if (c.kind == GEMM_DOT && g.fold != 0) {
+        // copies as an outer batch: the folded operand takes every copy
+        const unsigned all = (unsigned)g.nr - 1;
+        if (g.fold == 1) { g.mA = 0; g.mB = all; } else { g.mA = all; g.mB = 0; }
+        g.fold = 0;
+    }
     if (c.swap) {
         // C^T = B^T A^T, written transposed
         g.A = g0.B; g.B = g0.A;
         g.M = g0.N; g.N = g0.M;
         g.transA = !g0.transB; g.transB = !g0.transA;
-        g.sAb = g0.sBb; g.sAi = g0.sBi; g.sBb = g0.sAb; g.sBi = g0.sAi;
+        g.sAb = g0.sBb; g.sAi = g0.sBi; g.sAr = g0.sBr; g.mA = g0.mB;
+        g.sBb = g0.sAb; g.sBi = g0.sAi; g.sBr = g0.sAr; g.mB = g0.mA;
         g.transC = !g0.transC;
+        g.fold = g.fold == 1 ? 2 : g.fold == 2 ? 1 : 0;
     }
     g.splits = c.splits;
     if (c.splits > 1 && !g.P) return hipErrorInvalidValue;
-    const size_t batches = (size_t)g.nbatch * g.nb * c.splits;
+    const int Mt = g.fold == 2 ? g.M * g.nr : g.M;
+    const int Nt = g.fold == 1 ? g.N * g.nr : g.N;
+    const size_t n_outer = g.fold == 0 ? (size_t)g.nr * g.nb : (size_t)g.nb;
+    const size_t batches = (size_t)g.nbatch * n_outer * c.splits;
     if (c.kind == GEMM_DOT) {
         if (g.transA) {
             if (g.transB) hipLaunchKernelGGL((k_cgemm_dot<true, true>), dim3((unsigned)batches), dim3(256), 0, s, g);
@@ -473,14 +551,14 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
         int bm = 128, bn = 128;
         if (c.kind == GEMM_MFMA_64x64) { bm = 64; bn = 64; }
         if (c.kind == GEMM_MFMA_128x16) { bm = 128; bn = 16; }
-        const size_t grid = (size_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * batches;
+        const size_t grid = (size_t)((Mt + bm - 1) / bm) * ((Nt + bn - 1) / bn) * batches;
         if (c.kind == GEMM_MFMA_128x128) launch_prec<2, 2, 2, 4>(g, precision, grid, s);
         else if (c.kind == GEMM_MFMA_64x64) launch_prec<2, 2, 1, 2>(g, precision, grid, s);
         else launch_prec<4, 1, 1, 1>(g, precision, grid, s);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || c.splits <= 1) return e;
-    const size_t per = (size_t)g.M * g.N * g.nbatch * g.nb;
+    const size_t per = (size_t)Mt * Nt * g.nbatch * n_outer;
     unsigned blocks = (unsigned)std::min<size_t>((per + 255) / 256, 1u << 16);
     hipLaunchKernelGGL(k_reduce_splitk, dim3(blocks), dim3(256), 0, s, g);
     return hipGetLastError();
@@ -488,5 +566,8 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
 
 int gemm_kind(const GemmArgs& g, int precision) {
     (void)precision;
-    return choose_gemm(g.M, g.N, g.K, g.nbatch).kind;
+    const int nr = g.nr < 1 ? 1 : g.nr;
+    const int Mt = (g.fold == 2 && nr > 1) ? g.M * nr : g.M;
+    const int Nt = (g.fold == 1 && nr > 1) ? g.N * nr : g.N;
+    return choose_gemm(g.M, g.N, g.K, g.nbatch, Mt, Nt).kind;
 }

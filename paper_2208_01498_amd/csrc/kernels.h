@@ -11,8 +11,10 @@ struct GatherArgs {
     const float2* src;
     float2* dst;
     const uint64_t* bits;     // bitstrings of the chunk (one per b)
-    uint32_t slice;
+    uint32_t slice;           // high bits of the slice index (the pass)
+    uint32_t dmask;           // low slice bits the leaf depends on
     int nb;                   // batch count (chunk if the leaf has outputs, else 1)
+    int nr;                   // copies: 2^popcount(dmask); copy c has low bits pdep(c, dmask)
     int n_mat, n_out, n_sl;
     int mat_src[TN_MAX_GATHER];
     int out_src[TN_MAX_GATHER];
@@ -46,8 +48,13 @@ struct GemmArgs {
     int transA, transB;       // A stored [K][M] / B stored [N][K]
     int nbatch;               // inner batch count (batch labels)
     int nb;                   // outer batch count (bitstrings)
+    int nr;                   // copies of C over the slice block, 1 if none
+    int fold;                 // 0: copies as an outer batch; 1: folded into N
+                              // (only B and C vary with it); 2: folded into M
+    unsigned mA, mB;          // fold 0: A's copy = pext(c, mA), B's copy = pext(c, mB)
     long long sAb, sBb, sCb;  // outer strides (elements); 0 = broadcast
     long long sAi, sBi, sCi;  // inner strides
+    long long sAr, sBr, sCr;  // slice-block strides; 0 = broadcast
 };
 
 hipError_t launch_gather(const GatherArgs& g, hipStream_t s);
@@ -58,11 +65,16 @@ struct GemmChoice {
     int splits;               // K ranges (1 = no split-K)
     int swap;                 // compute C^T = B^T A^T
 };
-// Kernel choice from the shape only (not from the outer batch count).
-GemmChoice choose_gemm(int M, int N, int K, int nbatch);
-size_t gemm_scratch_elems(int M, int N, int K, int nbatch, int nb);
+// Kernel choice.  The arithmetic (dot-product kernel or MFMA kernel, and the
+// number of K ranges) depends on the per-matrix shape M, N, K and the inner
+// batch only; the tile shape may also depend on the folded sizes, which does
+// not change any element's summation order.
+GemmChoice choose_gemm(int M, int N, int K, int nbatch, int Mt = 0, int Nt = 0);
+size_t gemm_scratch_elems(int M, int N, int K, int nbatch, int nouter);
 hipError_t launch_gemm(const GemmArgs& g, int precision, hipStream_t s);
 int gemm_kind(const GemmArgs& g, int precision);
 hipError_t launch_zero_acc(double2* acc, int nb, hipStream_t s);
-hipError_t launch_accumulate(double2* acc, const float2* v, int nb, int v_has_b, hipStream_t s);
+// acc[b] += sum over r < nr (ascending) of v[r * vr + (v_has_b ? b : 0)]
+hipError_t launch_accumulate(double2* acc, const float2* v, int nb, int v_has_b, int nr,
+                             long long vr, hipStream_t s);
 hipError_t launch_finalize(double2* acc, int nb, double sre, double sim, hipStream_t s);

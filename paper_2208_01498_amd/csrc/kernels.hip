@@ -18,10 +18,17 @@
 // ---------------------------------------------------------------------------
 __global__ void k_gather_leaf(GatherArgs g) {
     const size_t per = size_t(1) << g.n_mat;
-    const size_t total = per * (size_t)g.nb;
+    const size_t total = per * (size_t)g.nb * (size_t)g.nr;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
-        const size_t b = idx >> g.n_mat;
+        const size_t outer = idx >> g.n_mat;
+        const size_t b = outer % g.nb;
+        // low slice bits of this copy: deposit the copy index into dmask
+        uint32_t c = (uint32_t)(outer / g.nb), slice = g.slice;
+        for (uint32_t m = g.dmask; m; m &= m - 1) {
+            if (c & 1) slice |= m & (~m + 1);
+            c >>= 1;
+        }
         const size_t j = idx & (per - 1);
         size_t src = 0;
         for (int p = 0; p < g.n_mat; ++p)
@@ -32,7 +39,7 @@ __global__ void k_gather_leaf(GatherArgs g) {
                 if ((x >> g.out_qubit[i]) & 1) src |= size_t(1) << g.out_src[i];
         }
         for (int i = 0; i < g.n_sl; ++i)
-            if ((g.slice >> g.sl_bit[i]) & 1) src |= size_t(1) << g.sl_src[i];
+            if ((slice >> g.sl_bit[i]) & 1) src |= size_t(1) << g.sl_src[i];
         g.dst[idx] = g.src[src];
     }
 }
@@ -80,13 +87,16 @@ __global__ void k_zero_acc(double2* acc, int nb) {
     if (b < nb) acc[b] = make_double2(0.0, 0.0);
 }
 
-__global__ void k_accumulate(double2* acc, const float2* v, int nb, int v_has_b) {
+__global__ void k_accumulate(double2* acc, const float2* v, int nb, int v_has_b, int nr,
+                             long long vr) {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < nb) {
-        const float2 x = v[v_has_b ? b : 0];
         double2 a = acc[b];
-        a.x += (double)x.x;
-        a.y += (double)x.y;
+        for (int r = 0; r < nr; ++r) {          // ascending slice order
+            const float2 x = v[(size_t)r * vr + (v_has_b ? b : 0)];
+            a.x += (double)x.x;
+            a.y += (double)x.y;
+        }
         acc[b] = a;
     }
 }
@@ -102,7 +112,7 @@ __global__ void k_finalize(double2* acc, int nb, double sre, double sim) {
 // ---------------------------------------------------------------------------
 // launchers
 hipError_t launch_gather(const GatherArgs& g, hipStream_t s) {
-    size_t total = (size_t(1) << g.n_mat) * (size_t)g.nb;
+    size_t total = (size_t(1) << g.n_mat) * (size_t)g.nb * (size_t)g.nr;
     unsigned blocks = (unsigned)((total + 255) / 256);
     if (blocks > 65536u) blocks = 65536u;
     if (blocks == 0) blocks = 1;
@@ -124,8 +134,10 @@ hipError_t launch_zero_acc(double2* acc, int nb, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_accumulate(double2* acc, const float2* v, int nb, int v_has_b, hipStream_t s) {
-    hipLaunchKernelGGL(k_accumulate, dim3((nb + 255) / 256), dim3(256), 0, s, acc, v, nb, v_has_b);
+hipError_t launch_accumulate(double2* acc, const float2* v, int nb, int v_has_b, int nr,
+                             long long vr, hipStream_t s) {
+    hipLaunchKernelGGL(k_accumulate, dim3((nb + 255) / 256), dim3(256), 0, s, acc, v, nb, v_has_b,
+                       nr, vr);
     return hipGetLastError();
 }
 

@@ -210,7 +210,6 @@ int parse_plan(const void* blob, size_t nbytes, PlanHost& p) {
     p.steps.resize(n_steps);
     std::vector<char> used(T, 0);
     double fps = 0.0, ftot = 0.0;
-    const int S = (int)n_sliced;
     for (uint32_t s = 0; s < n_steps; ++s) {
         Step& st = p.steps[s];
         st.a = (int)r.u32();
@@ -312,8 +311,8 @@ int parse_plan(const void* blob, size_t nbytes, PlanHost& p) {
         p.dep[st.c] = st.dep_mask;
         p.max_rank = std::max(p.max_rank, (int)oc.size());
         fps += st.flops_per_b;
-        if (st.dep_mask == 0) ftot += st.flops_per_b;
-        else ftot += st.flops_per_b * std::ldexp(1.0, S - __builtin_ctz(st.dep_mask));
+        // every slice value a step depends on, once (all slices in one pass)
+        ftot += st.flops_per_b * std::ldexp(1.0, __builtin_popcount(st.dep_mask));
     }
     uint32_t nmeta = r.u32();
     if (!r.ok || nmeta > 64) return fail("meta");
@@ -350,9 +349,11 @@ int parse_plan(const void* blob, size_t nbytes, PlanHost& p) {
 // loop; all others live from their producing step to their consuming step.
 // Buffers are placed first-fit by decreasing size, never overlapping a
 // buffer whose lifetime overlaps.
-MemPlan plan_memory(const PlanHost& p, int chunk) {
+MemPlan plan_memory(const PlanHost& p, int chunk, int r) {
     MemPlan mp;
     mp.chunk = chunk;
+    mp.r = r;
+    const uint32_t low = (1u << r) - 1;
     const int nL = (int)p.leaves.size();
     const int T = (int)p.rank.size();
     const int S = (int)p.sliced.size();
@@ -363,8 +364,12 @@ MemPlan plan_memory(const PlanHost& p, int chunk) {
     mp.scratch_off.assign(p.steps.size(), kNone);
     struct Buf { size_t bytes; int start, end; size_t* off; };
     std::vector<Buf> bufs;
-    auto elems = [&](int rk, bool hb) { return (size_t(1) << rk) * (hb ? (size_t)chunk : 1); };
-    auto period = [&](uint32_t m) { return m ? __builtin_ctz(m) : S + 1; };
+    // a tensor whose subtree holds low slice bits exists once per slice of the
+    // block; recomputation follows the high bits, pass by pass
+    auto elems = [&](int rk, bool hb, uint32_t dep) {
+        return (size_t(1) << rk) * (hb ? (size_t)chunk : 1) * (size_t(1) << __builtin_popcount(dep & low));
+    };
+    auto period = [&](uint32_t m) { m >>= r; return m ? __builtin_ctz(m) : S + 1; };
     const int INF = std::numeric_limits<int>::max();
     // accumulators + bitstrings + root
     size_t fixed = 0;
@@ -386,7 +391,7 @@ MemPlan plan_memory(const PlanHost& p, int chunk) {
             else if (period(p.steps[q].dep_mask) < period(p.dep[t])) start = -1, end = INF;
             else end = q;
         }
-        bufs.push_back({elems(p.rank[t], p.has_b[t]) * 8, start, end, &mp.tensor_off[t]});
+        bufs.push_back({elems(p.rank[t], p.has_b[t], p.dep[t]) * 8, start, end, &mp.tensor_off[t]});
     }
     // a permuted operand is re-permuted only when the operand itself changed,
     // so its copy lives like the operand
@@ -400,15 +405,16 @@ MemPlan plan_memory(const PlanHost& p, int chunk) {
         int a0, a1;
         if (st.permA) {
             operand_life(st.a, (int)s, a0, a1);
-            bufs.push_back({elems((int)st.orderA.size(), st.hbA) * 8, a0, a1, &mp.permA_off[s]});
+            bufs.push_back({elems((int)st.orderA.size(), st.hbA, p.dep[st.a]) * 8, a0, a1, &mp.permA_off[s]});
         }
         if (st.permB) {
             operand_life(st.b, (int)s, a0, a1);
-            bufs.push_back({elems((int)st.orderB.size(), st.hbB) * 8, a0, a1, &mp.permB_off[s]});
+            bufs.push_back({elems((int)st.orderB.size(), st.hbB, p.dep[st.b]) * 8, a0, a1, &mp.permB_off[s]});
         }
         const int M = 1 << st.m_bits, N = 1 << st.n_bits, K = 1 << st.k_bits;
         const int Mk = st.swapC ? N : M, Nk = st.swapC ? M : N;
-        size_t se = gemm_scratch_elems(Mk, Nk, K, 1 << st.batch_bits, st.hbC ? chunk : 1);
+        const int nouter = (st.hbC ? chunk : 1) * (1 << __builtin_popcount(st.dep_mask & low));
+        size_t se = gemm_scratch_elems(Mk, Nk, K, 1 << st.batch_bits, nouter);
         if (se) bufs.push_back({se * 8, (int)s, (int)s, &mp.scratch_off[s]});
     }
     for (auto& b : bufs) b.bytes = (b.bytes + 255) / 256 * 256;
@@ -439,10 +445,11 @@ MemPlan plan_memory(const PlanHost& p, int chunk) {
 
 }  // namespace tn
 
-const tn::MemPlan& tn_plan::mem(int chunk) {
+const tn::MemPlan& tn_plan::mem(int chunk, int r) {
     std::lock_guard<std::mutex> g(mcache);
-    auto it = memcache.find(chunk);
+    const long long key = (long long)chunk * 64 + r;
+    auto it = memcache.find(key);
     if (it != memcache.end()) return it->second;
-    auto& v = memcache[chunk] = tn::plan_memory(host, chunk);
+    auto& v = memcache[key] = tn::plan_memory(host, chunk, r);
     return v;
 }

@@ -75,16 +75,28 @@ static void fill_perm(PermArgs& pa, const int* map, int r) {
     pa.nn = m;
 }
 
-static int choose_chunk(const tn_plan* plan, int nb, size_t ws_bytes) {
+// Execution shape for a workspace: r low slice bits are computed together
+// as a slice block (2^r slices per pass), `chunk` bitstrings per pass.  The
+// largest block that fits with at least one bitstring is taken (a forced r
+// from the context option wins when it fits), then the largest chunk.
+static bool choose_shape(const tn_plan* plan, int nb, size_t ws_bytes, int force_r, int& r_out,
+                         int& chunk_out) {
     tn_plan* pl = const_cast<tn_plan*>(plan);
-    if (pl->mem(1).bytes > ws_bytes) return 0;
+    const int S = (int)plan->host.sliced.size();
+    int r = -1;
+    if (force_r >= 0 && force_r <= S && pl->mem(1, force_r).bytes <= ws_bytes) r = force_r;
+    for (int rr = S; r < 0 && rr >= 0; --rr)
+        if (pl->mem(1, rr).bytes <= ws_bytes) r = rr;
+    if (r < 0) return false;
     int lo = 1, hi = nb;
     while (lo < hi) {
         int mid = (lo + hi + 1) / 2;
-        if (pl->mem(mid).bytes <= ws_bytes) lo = mid;
+        if (pl->mem(mid, r).bytes <= ws_bytes) lo = mid;
         else hi = mid - 1;
     }
-    return lo;
+    r_out = r;
+    chunk_out = lo;
+    return true;
 }
 
 int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int precision,
@@ -92,20 +104,23 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
     const PlanHost& p = plan->host;
     tn_plan* pl = const_cast<tn_plan*>(plan);
     tn_exec_stats es{};
-    const int chunk = choose_chunk(plan, nb, ws_bytes);
-    if (chunk <= 0) {
+    int r = 0, chunk = 0;
+    if (!choose_shape(plan, nb, ws_bytes, ctx ? ctx->force_slice_block : -1, r, chunk)) {
         set_error("one bitstring of this plan needs more workspace than available");
         return TN_ENOMEM;
     }
-    const MemPlan& mp = pl->mem(chunk);
+    const MemPlan& mp = pl->mem(chunk, r);
     const int S = (int)p.sliced.size();
-    const uint64_t nslices = 1ull << S;
+    const int R = 1 << r;
+    const uint32_t low = (uint32_t)R - 1;
+    const uint64_t ngroups = 1ull << (S - r);
     const int nL = (int)p.leaves.size();
     es.chunk = chunk;
+    es.slice_block = R;
     // event timing: pairs (start, end) per launch, harvested at every chunk
     // end and whenever the pool is used up
     const bool prof = ctx && ctx->profile && stats;
-    struct Rec { int kind; double flops, bytes; };
+    struct Rec { int kind; };
     std::vector<Rec> recs;
     size_t ev_used = 0;
     auto harvest = [&]() -> int {
@@ -137,7 +152,7 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
         es.bytes[kind] += bytes;
         if (!prof) return TN_OK;
         HIPCHK(ctx, hipEventRecord(ctx->events[ev_used + 1], stream));
-        recs.push_back({kind, flops, bytes});
+        recs.push_back({kind});
         ev_used += 2;
         return TN_OK;
     };
@@ -148,24 +163,41 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
         double2* d_acc = reinterpret_cast<double2*>(ws + mp.acc_off);
         HIPCHK(ctx, hipMemcpyAsync(d_bits, bits + c0, sizeof(uint64_t) * cb, hipMemcpyHostToDevice, stream));
         HIPCHK(ctx, launch_zero_acc(d_acc, cb, stream));
+        // tensor layout in the workspace: [copy][bitstring][labels], one copy
+        // per value of the low slice bits the tensor depends on
+        auto dlow = [&](int t) -> uint32_t { return p.dep[t] & low; };
+        auto ncopy = [&](int t) -> int { return 1 << __builtin_popcount(dlow(t)); };
+        auto nbt = [&](int t) { return p.has_b[t] ? cb : 1; };
+        auto per_r = [&](int t) -> long long { return (1ll << p.rank[t]) * nbt(t); };
+        // positions of the bits of `sub` within the bits of `sup` (pext)
+        auto pext_mask = [](uint32_t sub, uint32_t sup) -> unsigned {
+            unsigned r = 0;
+            int k = 0;
+            for (uint32_t m = sup; m; m &= m - 1, ++k)
+                if (sub & (m & (~m + 1))) r |= 1u << k;
+            return r;
+        };
         auto tensor_ptr = [&](int t) -> float2* {
             if (t < nL && p.leaves[t].identity)
                 return reinterpret_cast<float2*>(plan->d_leaves) + p.leaves[t].dev_off;
             return reinterpret_cast<float2*>(ws + mp.tensor_off[t]);
         };
-        for (uint64_t s = 0; s < nslices; ++s) {
-            const uint32_t changed = s == 0 ? 0xffffffffu : (uint32_t)(s ^ (s - 1));
+        for (uint64_t G = 0; G < ngroups; ++G) {
+            const uint32_t changed = G == 0 ? 0xffffffffu : (uint32_t)(G ^ (G - 1));
+            auto redo = [&](uint32_t dep) { return G == 0 || ((dep >> r) & changed); };
+            const uint32_t slice0 = (uint32_t)(G << r);
             auto gather = [&](int t) -> int {
                 if (t >= nL) return TN_OK;
                 const Leaf& lf = p.leaves[t];
-                if (lf.identity) return TN_OK;
-                if (!(s == 0 || (lf.slice_mask & changed))) return TN_OK;
+                if (lf.identity || !redo(lf.slice_mask)) return TN_OK;
                 GatherArgs g{};
                 g.src = reinterpret_cast<const float2*>(plan->d_leaves) + lf.dev_off;
                 g.dst = tensor_ptr(t);
                 g.bits = d_bits;
-                g.slice = (uint32_t)s;
+                g.slice = slice0;
+                g.dmask = dlow(t);
                 g.nb = lf.has_b ? cb : 1;
+                g.nr = ncopy(t);
                 g.n_mat = lf.n_mat;
                 g.n_out = lf.n_out;
                 g.n_sl = lf.n_sl;
@@ -176,7 +208,7 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                 if (rc0) return rc0;
                 HIPCHK(ctx, launch_gather(g, stream));
                 es.kernels_gather++;
-                return ev_end(5, 0.0, 8.0 * std::ldexp(1.0, g.n_mat) * g.nb);
+                return ev_end(5, 0.0, 8.0 * std::ldexp(1.0, g.n_mat) * g.nb * g.nr);
             };
             if (p.steps.empty()) {
                 int rc = gather(0);
@@ -184,7 +216,7 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
             }
             for (size_t si = 0; si < p.steps.size(); ++si) {
                 const Step& st = p.steps[si];
-                if (!(s == 0 || (st.dep_mask & changed))) {
+                if (!redo(st.dep_mask)) {
                     es.steps_reused++;
                     continue;
                 }
@@ -194,62 +226,65 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                 if (rc) return rc;
                 const float2* pa = tensor_ptr(st.a);
                 const float2* pb = tensor_ptr(st.b);
-                const bool redoA = (s == 0) || (p.dep[st.a] & changed);
-                const bool redoB = (s == 0) || (p.dep[st.b] & changed);
-                if (st.permA && !redoA) pa = reinterpret_cast<float2*>(ws + mp.permA_off[si]);
-                if (st.permB && !redoB) pb = reinterpret_cast<float2*>(ws + mp.permB_off[si]);
-                if (st.permA && redoA) {
-                    PermArgs a{};
-                    fill_perm(a, st.permA_map, (int)st.orderA.size());
-                    a.src = pa;
-                    a.dst = reinterpret_cast<float2*>(ws + mp.permA_off[si]);
-                    a.nb = st.hbA ? cb : 1;
-                    rc = ev_begin();
-                    if (rc) return rc;
-                    HIPCHK(ctx, launch_permute(a, stream));
-                    es.kernels_permute++;
-                    es.permute_bytes += 16.0 * std::ldexp(1.0, a.rank) * a.nb;
-                    rc = ev_end(4, 0.0, 16.0 * std::ldexp(1.0, a.rank) * a.nb);
-                    if (rc) return rc;
-                    pa = a.dst;
-                }
-                if (st.permB && redoB) {
-                    PermArgs a{};
-                    fill_perm(a, st.permB_map, (int)st.orderB.size());
-                    a.src = pb;
-                    a.dst = reinterpret_cast<float2*>(ws + mp.permB_off[si]);
-                    a.nb = st.hbB ? cb : 1;
-                    rc = ev_begin();
-                    if (rc) return rc;
-                    HIPCHK(ctx, launch_permute(a, stream));
-                    es.kernels_permute++;
-                    es.permute_bytes += 16.0 * std::ldexp(1.0, a.rank) * a.nb;
-                    rc = ev_end(4, 0.0, 16.0 * std::ldexp(1.0, a.rank) * a.nb);
-                    if (rc) return rc;
-                    pb = a.dst;
+                const bool redoA = redo(p.dep[st.a]);
+                const bool redoB = redo(p.dep[st.b]);
+                for (int w = 0; w < 2; ++w) {
+                    const bool perm = w ? st.permB : st.permA;
+                    if (!perm) continue;
+                    const int t = w ? st.b : st.a;
+                    float2* dst = reinterpret_cast<float2*>(ws + (w ? mp.permB_off[si] : mp.permA_off[si]));
+                    if (w ? redoB : redoA) {
+                        PermArgs a{};
+                        fill_perm(a, w ? st.permB_map : st.permA_map, (int)(w ? st.orderB : st.orderA).size());
+                        a.src = w ? pb : pa;
+                        a.dst = dst;
+                        a.nb = nbt(t) * ncopy(t);
+                        rc = ev_begin();
+                        if (rc) return rc;
+                        HIPCHK(ctx, launch_permute(a, stream));
+                        es.kernels_permute++;
+                        es.permute_bytes += 16.0 * std::ldexp(1.0, a.rank) * a.nb;
+                        rc = ev_end(4, 0.0, 16.0 * std::ldexp(1.0, a.rank) * a.nb);
+                        if (rc) return rc;
+                    }
+                    if (w) pb = dst; else pa = dst;
                 }
                 const long long nbat = 1ll << st.batch_bits;
                 const long long M = 1ll << st.m_bits, N = 1ll << st.n_bits, K = 1ll << st.k_bits;
+                const uint32_t DA = dlow(st.a), DB = dlow(st.b), DC = dlow(st.c);
                 GemmArgs g{};
                 const int nbC = st.hbC ? cb : 1;
                 float2* pc = tensor_ptr(st.c);
-                if (!st.swapC) {
-                    g.A = pa; g.B = pb; g.C = pc;
-                    g.M = (int)M; g.N = (int)N; g.K = (int)K;
-                    g.transA = st.transA; g.transB = st.transB;
-                    g.sAb = st.hbA ? nbat * M * K : 0; g.sAi = M * K;
-                    g.sBb = st.hbB ? nbat * K * N : 0; g.sBi = K * N;
-                } else {
-                    // C^T = B^T A^T
-                    g.A = pb; g.B = pa; g.C = pc;
-                    g.M = (int)N; g.N = (int)M; g.K = (int)K;
-                    g.transA = !st.transB; g.transB = !st.transA;
-                    g.sAb = st.hbB ? nbat * K * N : 0; g.sAi = K * N;
-                    g.sBb = st.hbA ? nbat * M * K : 0; g.sBi = M * K;
+                // operands in kernel roles (C stored [N][M] -> C^T = B^T A^T)
+                const float2 *ka = pa, *kb = pb;
+                int tA = st.transA, tB = st.transB;
+                bool hA = st.hbA, hB = st.hbB;
+                unsigned mA = pext_mask(DA, DC), mB = pext_mask(DB, DC);
+                long long km = M, kn = N, lenA = M * K, lenB = K * N;
+                long long pA = per_r(st.a), pB = per_r(st.b);
+                if (st.swapC) {
+                    std::swap(ka, kb);
+                    tA = !st.transB; tB = !st.transA;
+                    std::swap(hA, hB); std::swap(mA, mB);
+                    std::swap(km, kn); std::swap(lenA, lenB); std::swap(pA, pB);
                 }
+                g.A = ka; g.B = kb; g.C = pc;
+                g.M = (int)km; g.N = (int)kn; g.K = (int)K;
+                g.transA = tA; g.transB = tB;
+                g.sAb = hA ? nbat * lenA : 0; g.sAi = lenA;
+                g.sBb = hB ? nbat * lenB : 0; g.sBi = lenB;
                 g.sCb = nbat * M * N; g.sCi = M * N;
                 g.nbatch = (int)nbat;
                 g.nb = nbC;
+                g.nr = ncopy(st.c);
+                const unsigned all = (unsigned)g.nr - 1;
+                g.mA = mA;
+                g.mB = mB;
+                g.sAr = mA ? pA : 0;
+                g.sBr = mB ? pB : 0;
+                g.sCr = g.nr > 1 ? per_r(st.c) : 0;
+                // copies fold into the free index of the only operand that has them
+                g.fold = (g.nr > 1 && mA == 0 && mB == all) ? 1 : (g.nr > 1 && mB == 0 && mA == all) ? 2 : 0;
                 if (mp.scratch_off[si] != std::numeric_limits<size_t>::max())
                     g.P = reinterpret_cast<float2*>(ws + mp.scratch_off[si]);
                 rc = ev_begin();
@@ -257,13 +292,17 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                 HIPCHK(ctx, launch_gemm(g, precision, stream));
                 es.kernels_gemm++;
                 es.steps_executed++;
-                es.algorithmic_flops += st.flops_per_b * nbC;
-                rc = ev_end(gemm_kind(g, precision), st.flops_per_b * nbC,
-                            8.0 * ((double)nbat * (M * K * (st.hbA ? nbC : 1) + K * N * (st.hbB ? nbC : 1) + M * N * nbC)));
+                const double mult = (double)nbC * g.nr;
+                es.algorithmic_flops += st.flops_per_b * mult;
+                rc = ev_end(gemm_kind(g, precision), st.flops_per_b * mult,
+                            8.0 * ((double)nbat * (M * K * (st.hbA ? nbC : 1) * ncopy(st.a) +
+                                                   K * N * (st.hbB ? nbC : 1) * ncopy(st.b) +
+                                                   M * N * nbC * g.nr)));
                 if (rc) return rc;
             }
             const int root = p.root;
-            HIPCHK(ctx, launch_accumulate(d_acc, tensor_ptr(root), cb, p.has_b[root], stream));
+            HIPCHK(ctx, launch_accumulate(d_acc, tensor_ptr(root), cb, p.has_b[root],
+                                          ncopy(root), per_r(root), stream));
         }
         HIPCHK(ctx, launch_finalize(d_acc, cb, p.scale.real(), p.scale.imag(), stream));
         HIPCHK(ctx, hipMemcpyAsync(out + 2 * (size_t)c0, d_acc, sizeof(double2) * cb, hipMemcpyDeviceToHost, stream));
@@ -354,7 +393,7 @@ int tn_plan_info(const tn_plan* plan, tn_plan_info_t* out) {
     out->reserved = 0;
     out->flops_per_slice_per_b = p.flops_per_slice_per_b;
     out->flops_total_per_b = p.flops_total_per_b;
-    size_t m1 = pl->mem(1).bytes, m2 = pl->mem(2).bytes;
+    size_t m1 = pl->mem(1, 0).bytes, m2 = pl->mem(2, 0).bytes;
     out->peak_bytes_per_b = m2 > m1 ? m2 - m1 : 0;
     out->peak_bytes_fixed = m1 > out->peak_bytes_per_b ? m1 - out->peak_bytes_per_b : 0;
     return TN_OK;
@@ -407,7 +446,7 @@ int tn_contract_amplitudes(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bit
     // workspace: the largest free region of the arena (all of it when the
     // serving loop is idle); wait for served batches to release memory when
     // not even one bitstring fits
-    const size_t need1 = const_cast<tn_plan*>(plan)->mem(1).bytes;
+    const size_t need1 = const_cast<tn_plan*>(plan)->mem(1, 0).bytes;
     if (need1 > ctx->arena_bytes) {
         set_error("one bitstring of this plan needs more workspace than the arena holds");
         return TN_ENOMEM;
@@ -489,6 +528,12 @@ int tn_kernel_permute(const void* src, void* dst, int32_t rank, const int32_t* p
 int tn_ctx_set_profiling(tn_ctx* ctx, int32_t on) {
     if (!ctx) return TN_EINVAL;
     ctx->profile = on != 0;
+    return TN_OK;
+}
+
+int tn_ctx_set_slice_block(tn_ctx* ctx, int32_t log2_block) {
+    if (!ctx || log2_block < -1 || log2_block > 30) { set_error("bad slice block"); return TN_EINVAL; }
+    ctx->force_slice_block = log2_block;
     return TN_OK;
 }
 

@@ -134,7 +134,7 @@ static void scheduler(tn_ctx* ctx) {
         }
         // admission: the largest chunk (<= total) whose workspace fits a free region
         size_t avail = largest_free(ctx);
-        size_t need1 = plan->mem(1).bytes;
+        size_t need1 = plan->mem(1, 0).bytes;
         if (need1 > avail) {
             // not admissible now: put the job back in arrival order and wait
             for (auto it = job.rbegin(); it != job.rend(); ++it) ctx->queue.push_front(*it);
@@ -154,10 +154,10 @@ static void scheduler(tn_ctx* ctx) {
         int lo = 1, hi = total;
         while (lo < hi) {
             int mid = (lo + hi + 1) / 2;
-            if (plan->mem(mid).bytes <= avail) lo = mid;
+            if (plan->mem(mid, 0).bytes <= avail) lo = mid;
             else hi = mid - 1;
         }
-        size_t bytes = plan->mem(lo).bytes;
+        size_t bytes = plan->mem(lo, 0).bytes;
         size_t off = 0;
         arena_alloc(ctx, bytes, &off);
         int64_t t = now_ns();
@@ -231,7 +231,7 @@ int tn_submit(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int32_t nb
     if (ctx->poisoned) { set_error("context poisoned"); return TN_EDEVICE; }
     for (int i = 0; i < nb; ++i)
         if (bits[i] & ~plan->host.out_mask) { set_error("bitstring has a bit at a position >= n_qubits"); return TN_EINVAL; }
-    if (const_cast<tn_plan*>(plan)->mem(1).bytes > ctx->arena_bytes) {
+    if (const_cast<tn_plan*>(plan)->mem(1, 0).bytes > ctx->arena_bytes) {
         set_error("one bitstring of this plan needs more workspace than the arena holds");
         return TN_ENOMEM;
     }

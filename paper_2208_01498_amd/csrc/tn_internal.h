@@ -96,6 +96,7 @@ int parse_plan(const void* blob, size_t n, PlanHost& p);   // TN_OK / TN_EINVAL
 // Buffer assignment for one chunk size.
 struct MemPlan {
     int chunk = 0;
+    int r = 0;                                  // log2 slices per pass
     size_t bytes = 0;                           // total workspace bytes
     std::vector<size_t> tensor_off;             // per tensor id (bytes), SIZE_MAX if none
     std::vector<size_t> permA_off, permB_off;   // per step, SIZE_MAX if none
@@ -104,7 +105,7 @@ struct MemPlan {
     size_t bits_off = 0;                        // bitstrings
     size_t maps_off = 0;                        // per-step tables (none yet)
 };
-MemPlan plan_memory(const PlanHost& p, int chunk);
+MemPlan plan_memory(const PlanHost& p, int chunk, int r);
 
 struct DevicePlan;
 
@@ -116,8 +117,9 @@ struct tn_plan {
     std::atomic<int> pending{0};
     int id = 0;
     std::mutex mcache;
-    std::map<int, tn::MemPlan> memcache;
-    const tn::MemPlan& mem(int chunk);
+    std::map<long long, tn::MemPlan> memcache;
+    // workspace layout for `chunk` bitstrings and 2^r slices per pass
+    const tn::MemPlan& mem(int chunk, int r);
 };
 
 namespace tn {
@@ -176,6 +178,7 @@ struct tn_ctx {
     // per-launch event timing (blocking calls only)
     bool profile = false;
     std::vector<hipEvent_t> events;
+    int force_slice_block = -1;          // log2 slices per pass, -1 = automatic
 };
 
 namespace tn {

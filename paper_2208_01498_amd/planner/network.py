@@ -9,6 +9,10 @@ executor can run it efficiently:
   at the next such gate on that qubit; a diagonal gate (CZ, CP, Z(theta))
   keeps the index of each of its qubits, so its factor is indexed by its input
   labels only and one label can be shared by several factors (a hyperedge);
+  optionally, a two-qubit gate of the form SWAP . D with D diagonal
+  (fSim(pi/2, phi)) is the diagonal factor D on its input labels followed by
+  an exchange of the two wires between the qubits (the plan builder keeps
+  whichever form gives the cheaper contraction);
 * a wire still in |0> (no non-diagonal gate yet) is a fixed index 0, which is
   substituted into every factor that touches it;
 * the last label of each qubit is the output index O_q: it is replaced by
@@ -66,15 +70,33 @@ class Network:
         return users
 
 
+# entries below this fraction of the largest are structural zeros (cos(pi/2)
+# evaluates to 6e-17, not 0)
+ZERO_TOL = 1e-14
+
+
+def _nz(m):
+    return np.abs(m) > ZERO_TOL * np.max(np.abs(m))
+
+
 def _is_diag(m):
-    return np.count_nonzero(m - np.diag(np.diag(m))) == 0
+    return not np.any(_nz(m) & ~np.eye(m.shape[0], dtype=bool))
+
+
+_SWAP_PATTERN = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], dtype=bool)
+
+
+def _is_swap_diag(m):
+    """A two-qubit matrix SWAP . D with D diagonal (nonzero pattern of SWAP),
+    e.g. fSim(pi/2, phi)."""
+    return m.shape == (4, 4) and np.array_equal(_nz(m), _SWAP_PATTERN)
 
 
 def _gate_pos(circ, qs):
     return np.mean([circ.positions[q] for q in qs], axis=0)
 
 
-def build_network(circ, simplify=True):
+def build_network(circ, simplify=True, swap_relabel=False, coarsen=0):
     n = circ.n
     labels = {}
     factors = []
@@ -115,6 +137,13 @@ def build_network(circ, simplify=True):
         if _is_diag(g.matrix):
             d = np.diag(g.matrix).reshape((2,) * len(qs))
             add_factor(d, [cur[q] for q in qs], gi, qs)
+        elif swap_relabel and len(qs) == 2 and _is_swap_diag(g.matrix):
+            # G = SWAP . D: a diagonal weight on the input wires, then the two
+            # wires exchange qubits (no new index)
+            m = g.matrix
+            d = np.array([[m[0, 0], m[2, 1]], [m[1, 2], m[3, 3]]], dtype=np.complex128)
+            add_factor(d, [cur[q] for q in qs], gi, qs)
+            cur[qs[0]], cur[qs[1]] = cur[qs[1]], cur[qs[0]]
         else:
             outs = [new_label(q, gi) for q in qs]
             t = g.matrix.reshape((2,) * (2 * len(qs)))
@@ -133,6 +162,8 @@ def build_network(circ, simplify=True):
     net = Network(n, labels, factors, scale, circ.positions)
     if simplify:
         simplify_network(net)
+        if coarsen:
+            coarsen_network(net, coarsen)
     _attach_scalar_gates(net, circ, scalar_gates)
     return net
 
@@ -231,4 +262,57 @@ def simplify_network(net, max_rank=None):
             if not alive[i].labels:
                 facs[0].gates |= alive[i].gates
     net.factors = facs
+    return net
+
+
+def coarsen_network(net, max_rank):
+    """Merge neighbouring factors (in float64, on the host) while the merged
+    factor keeps at most ``max_rank`` labels and at most one label more than
+    the larger of the two: fewer, larger leaves, so each amplitude term passes
+    through fewer single-precision roundings of leaf entries and the plan has
+    fewer tiny steps."""
+    labels = net.labels
+    alive = {i: f for i, f in enumerate(net.factors)}
+    users = {}
+    for i, f in alive.items():
+        for l in f.labels:
+            users.setdefault(l, set()).add(i)
+    nid = len(net.factors)
+
+    def merged(i, j):
+        f, g = alive[i], alive[j]
+        u = set(f.labels) | set(g.labels)
+        return set(x for x in u if labels[x].kind == "out" or len(users[x] - {i, j}) > 0)
+
+    while True:
+        best = None
+        for i in sorted(alive):
+            f = alive[i]
+            for l in f.labels:
+                for j in users[l]:
+                    if j <= i or j not in alive:
+                        continue
+                    g = alive[j]
+                    keep = merged(i, j)
+                    if len(keep) > max_rank or len(keep) > max(len(f.labels), len(g.labels)) + 1:
+                        continue
+                    key = (len(keep), -len(set(f.labels) & set(g.labels)), i, j)
+                    if best is None or key < best[0]:
+                        best = (key, i, j, keep)
+        if best is None:
+            break
+        _, i, j, keep = best
+        f, g = alive[i], alive[j]
+        h = contract_factors(f, g, keep)
+        for x in f.labels:
+            users[x].discard(i)
+        for x in g.labels:
+            users[x].discard(j)
+        del alive[i]
+        del alive[j]
+        alive[nid] = h
+        for x in h.labels:
+            users.setdefault(x, set()).add(nid)
+        nid += 1
+    net.factors = [alive[i] for i in sorted(alive)]
     return net

@@ -102,21 +102,26 @@ class Plan:
 
 
 def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
-              n_circles=24, trials=1, objective="time"):
+              n_circles=24, trials=1, objective="time", coarsen=0):
     """Build a plan.  ``n_slices``: number of sliced labels (log2 of the slice
     count), or None to slice until the widest per-slice intermediate is at
     most ``target_width`` (log2 elements, batch included)."""
-    net = build_network(circ)
+    from .network import _is_swap_diag
+    forms = [False]
+    if any(len(g.qubits) == 2 and _is_swap_diag(g.matrix) for g in circ.gates):
+        forms.append(True)
     best = None
-    for t in range(trials):
-        tb = TreeBuilder(net, np.random.Generator(np.random.PCG64(seed + t)),
-                         bottom=bottom, n_circles=n_circles)
-        root = tb.build()
-        steps = tree_steps(root, len(net.factors))
-        st = plan_stats(net, steps, B=1)
-        if best is None or st["flops"] < best[0]:
-            best = (st["flops"], steps)
-    steps = best[1]
+    for swap_relabel in forms:
+        net = build_network(circ, swap_relabel=swap_relabel, coarsen=coarsen)
+        for t in range(trials):
+            tb = TreeBuilder(net, np.random.Generator(np.random.PCG64(seed + t)),
+                             bottom=bottom, n_circles=n_circles)
+            root = tb.build()
+            steps = tree_steps(root, len(net.factors))
+            st = plan_stats(net, steps, B=1)
+            if best is None or st["flops"] < best[0]:
+                best = (st["flops"], steps, net)
+    steps, net = best[1], best[2]
     sliced = []
     total = None
     predicted = None

@@ -15,10 +15,11 @@ import math
 
 class SliceModel:
     def __init__(self, net, steps, B=1, peak_flops=157.3e12 * 0.6, peak_bw=8.0e12 * 0.6,
-                 launch=4e-6, objective="time"):
+                 launch=4e-6, objective="time", blocked=True):
         self.net = net
         self.steps = steps
         self.B = B
+        self.blocked = blocked
         self.peak_flops, self.peak_bw, self.launch = peak_flops, peak_bw, launch
         self.objective = objective
         self.is_out = {l: lab.kind == "out" for l, lab in net.labels.items()}
@@ -102,14 +103,22 @@ class SliceModel:
             ub = sum(self.bits[l] for l in u if l not in Sset)
             cb = sum(self.bits[l] for l in lc if l not in Sset)
             f = 8.0 * 2.0 ** ub * bsz
-            reps = 2.0 ** (nS - min(hit)) if hit else 1.0
+            if self.blocked:
+                # all slices in one pass: one copy per value of the sliced
+                # labels in the step's subtree
+                reps = 2.0 ** len(hit)
+            else:
+                reps = 2.0 ** (nS - min(hit)) if hit else 1.0
             self.last_flops += f * reps
             if self.objective == "time":
                 ab = sum(self.bits[l] for l in la if l not in Sset)
                 bbits = sum(self.bits[l] for l in lb if l not in Sset)
                 byt = 8.0 * (2.0 ** ab * (self.B if ha else 1) + 2.0 ** bbits * (self.B if hb else 1)
                              + 2.0 ** cb * bsz)
-                total += reps * (max(f / self.peak_flops, byt / self.peak_bw) + self.launch)
+                if self.blocked:
+                    total += max(reps * f / self.peak_flops, reps * byt / self.peak_bw) + self.launch
+                else:
+                    total += reps * (max(f / self.peak_flops, byt / self.peak_bw) + self.launch)
             else:
                 total += f * reps
             width = max(width, cb + math.log2(bsz))

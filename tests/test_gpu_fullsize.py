@@ -1,0 +1,87 @@
+"""GPU checks at the workloads' full sizes, where the CPU oracle cannot
+compute the amplitudes: identities that hold at any size (mirror circuits),
+agreement across precisions and slice blocks, and the Porter-Thomas mean,
+plus exact parity on the same circuit families at sizes the oracle handles.
+"""
+import numpy as np
+import pytest
+
+from circuits import (make_config, lattice_circuit, mirror, random_bitstrings,
+                      iqp_lattice_circuit)
+from oracle import statevector_amplitudes, iqp_amplitudes_transfer
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+    from paper_2208_01498_amd import binding as B
+    free, _ = torch.cuda.mem_get_info(0)
+    e = B.Engine(0, arena_bytes=int(min(free - (8 << 30), 200 << 30)))
+    yield e
+    e.close()
+
+
+def _plan(circ, ns, B):
+    from paper_2208_01498_amd.planner.plan import make_plan
+    return make_plan(circ, n_slices=ns, B=B)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-5), (2, 1e-3)])
+def test_mirror_8x8_depth16_shape(eng, prec, tol):
+    """C^dag C for an 8x8 depth-8 Haar + CZ circuit (the depth-16 network
+    shape), 2^10 slices: a(0) = 1 and a(x != 0) = 0."""
+    c = mirror(lattice_circuit(8, 8, 8, 3000, "haar", "cz"))
+    words = np.concatenate([[0], random_bitstrings(64, 3, 3001)]).astype(np.uint64)
+    print("case mirror 8x8 d8+inverse, prec", prec, flush=True)
+    plan = _plan(c, 10, len(words))
+    got = eng.amplitudes(eng.load(plan.to_blob()), words, prec)
+    print("a(0) - 1 =", got[0] - 1, "max |a(x!=0)| =", np.abs(got[1:]).max(), flush=True)
+    assert abs(got[0] - 1) <= tol
+    assert np.abs(got[1:]).max() <= tol
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_same_family_as_headline_vs_statevector(eng, prec):
+    """Haar SU(2) + CZ, depth 16, 2^6 slices, at 4x5 (the oracle's size)."""
+    c = lattice_circuit(4, 5, 16, 3010, "haar", "cz")
+    words = random_bitstrings(20, 32, 3011)
+    print("case 4x5 d16 haar cz prec", prec, flush=True)
+    plan = _plan(c, 6, len(words))
+    got = eng.amplitudes(eng.load(plan.to_blob()), words, prec)
+    ref = statevector_amplitudes(c, words)
+    err = (np.abs(got - ref) / np.maximum(np.abs(ref), 2.0 ** (-c.n / 2))).max()
+    print("max err", err, "max plain relative", (np.abs(got - ref) / np.abs(ref)).max(), flush=True)
+    assert err <= (1e-5 if prec == 0 else 1e-3)
+
+
+def test_headline_precisions_agree_and_porter_thomas(eng):
+    """The 8x8 depth-16 workload itself on 8 of its bitstrings: FP32 and
+    split-bf16 agree within 1e-3, and the mean of 2^n |a|^2 is near 1."""
+    from paper_2208_01498_amd import binding as B
+    circ, words, _ = make_config("cfg3")
+    words = words[:8]
+    print("case cfg3 8 bitstrings", flush=True)
+    plan = _plan(circ, 10, len(words))
+    p = eng.load(plan.to_blob())
+    a = eng.amplitudes(p, words, B.TN_FP32_4M)
+    b = eng.amplitudes(p, words, B.TN_SPLIT_BF16)
+    rel = np.abs(a - b) / np.abs(a)
+    pt = np.mean((2.0 ** 64) * np.abs(a) ** 2)
+    print("fp32 vs bf16x3 max rel", rel.max(), "Porter-Thomas mean", pt, flush=True)
+    assert rel.max() <= 1e-3
+    assert 0.2 <= pt <= 4.0
+
+
+def test_iqp48_vs_closed_form(eng):
+    """The IQP workload (6x8 grid, CP within distance 2): every one of its
+    1024 bitstrings against the column transfer-matrix closed form."""
+    circ, words, _ = make_config("cfg4")
+    print("case cfg4 1024 bitstrings", flush=True)
+    plan = _plan(circ, 0, len(words))
+    got = eng.amplitudes(eng.load(plan.to_blob()), words, 0)
+    ref = iqp_amplitudes_transfer(circ, words)
+    err = (np.abs(got - ref) / np.maximum(np.abs(ref), 2.0 ** (-circ.n / 2))).max()
+    print("max err", err, "max plain relative", (np.abs(got - ref) / np.abs(ref)).max(), flush=True)
+    assert err <= 1e-5
