@@ -59,6 +59,91 @@ def cpu_baseline(circ, word, seconds=20.0, width=24, seed=0):
                       "slice count" % (done, len(labels), el)}
 
 
+def serve_bench(args):
+    """The served mixed stream: requests drawn uniformly from four circuit
+    families (three instances each, all plans resident), 1..64 bitstrings
+    each, Poisson arrivals at 0.7 x the measured saturation throughput."""
+    import numpy as np
+    import torch
+    from circuits import random_bitstrings
+    from circuits.families import serving_pool
+    from paper_2208_01498_amd.planner.plan import make_plan
+    from paper_2208_01498_amd import binding as B
+    pool = serving_pool()
+    t = time.perf_counter()
+    plans = [make_plan(c, n_slices=ns, B=32) for _, c, ns in pool]
+    log("12 plans built in %.1f s" % (time.perf_counter() - t))
+    free, _ = torch.cuda.mem_get_info(0)
+    eng = B.Engine(0, arena_bytes=int(free - (8 << 30)))
+    B.tn_server_config(eng.ctx, args.slots, 64)
+    hs = [eng.load(p.to_blob()) for p in plans]
+    rng = np.random.Generator(np.random.PCG64(5002))
+    fams = sorted(set(f for f, _, _ in pool))
+
+    def draw(i):
+        f = fams[int(rng.integers(len(fams)))]
+        idx = [k for k, (ff, _, _) in enumerate(pool) if ff == f]
+        k = idx[int(rng.integers(len(idx)))]
+        nb = int(rng.integers(1, 65))
+        return k, random_bitstrings(pool[k][1].n, nb, 90000 + i)
+
+    def run(reqs, arrivals):
+        t0 = time.perf_counter()
+        pending = {}
+        done = {}
+        i = 0
+        while i < len(reqs) or pending:
+            now = time.perf_counter() - t0
+            while i < len(reqs) and arrivals[i] <= now:
+                k, w = reqs[i]
+                pending[B.tn_submit(eng.ctx, hs[k], w, 0)] = (i, len(w))
+                i += 1
+            for tk in list(pending):
+                j, n = pending[tk]
+                r = B.tn_poll(eng.ctx, tk, n)
+                if r is not None:
+                    done[j] = r
+                    del pending[tk]
+                    log("request %d (%s, %d bitstrings) done after %.2f s" % (
+                        j, pool[reqs[j][0]][0], n,
+                        (r[1]["t_end_ns"] - r[1]["t_arrive_ns"]) * 1e-9))
+            time.sleep(0.0005)
+        return done, time.perf_counter() - t0
+
+    # saturation: a burst of requests submitted at once
+    burst = [draw(i) for i in range(args.serve_burst)]
+    done, el = run(burst, [0.0] * len(burst))
+    sat = len(burst) / el
+    log("saturation: %d requests in %.1f s -> %.3f req/s" % (len(burst), el, sat))
+    lam = 0.7 * sat
+    reqs = [draw(1000 + i) for i in range(args.serve_requests)]
+    gaps = rng.exponential(1.0 / lam, size=len(reqs))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    done, el = run(reqs, arrivals)
+    lat = np.array([(done[j][1]["t_end_ns"] - done[j][1]["t_arrive_ns"]) * 1e-9 for j in range(len(reqs))])
+    amps = sum(len(w) for _, w in reqs)
+    # the same request alone gives the same numbers
+    same = True
+    for j in range(min(6, len(reqs))):
+        k, w = reqs[j]
+        same &= bool(np.array_equal(eng.amplitudes(hs[k], w, 0), done[j][0]))
+    per_fam = {}
+    for j, (k, w) in enumerate(reqs):
+        per_fam.setdefault(pool[k][0], []).append(lat[j])
+    out = {"metric": "p50/p99 served latency, mixed stream", "unit": "s",
+           "p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+           "req_per_s": len(reqs) / el, "amplitudes_per_s": amps / el,
+           "lambda_req_per_s": lam, "saturation_req_per_s": sat, "n_requests": len(reqs),
+           "slots": args.slots, "alone_equals_mixed": same,
+           "p50_by_family": {f: float(np.percentile(v, 50)) for f, v in per_fam.items()},
+           "config": {"workload": "served mix: 5x5 d10, 6x6 d12, 8x8 d16 (2^10 slices) "
+                                  "Haar SU(2)+CZ lattices and 3x3x4 SU(4) stack, "
+                                  "1-64 bitstrings per request, Poisson arrivals"},
+           "data": "synthetic"}
+    print(json.dumps(out), flush=True)
+    eng.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,12 +158,18 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--serve", action="store_true", help="served mixed stream instead")
+    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serve-burst", type=int, default=16)
+    ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(slices would shard across GPUs with one all-reduce of the FP64 sums)",
               file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        return serve_bench(args)
 
     import numpy as np
     import torch

@@ -262,11 +262,15 @@ def make_config(name, seed=None):
 
 
 def serving_pool(seed=5100):
-    """Circuit families of the served mixed stream, three instances each."""
+    """Circuit families of the served mixed stream, three instances each:
+    5x5 depth 10, 6x6 depth 12 and 8x8 depth 16 lattice circuits of the
+    headline family (Haar SU(2) + CZ; the stream does not name a gate set),
+    and the (2+1)-dimensional 3x3x4 stack with 10 layers of SU(4) gates.
+    Returns a list of (family, circuit, slices log2)."""
     pool = []
     for j in range(3):
-        pool.append(("5x5d10", lattice_circuit(5, 5, 10, seed + j, "sqrt", "cz", f"mix5x5d10_{j}")))
-        pool.append(("6x6d12", lattice_circuit(6, 6, 12, seed + 10 + j, "sqrt", "fsim", f"mix6x6d12_{j}")))
-        pool.append(("8x8d16", lattice_circuit(8, 8, 16, seed + 20 + j, "haar", "cz", f"mix8x8d16_{j}")))
-        pool.append(("3x3x4", stack3d_circuit(3, 3, 4, 10, seed + 30 + j, f"mix3x3x4_{j}")))
+        pool.append(("5x5d10", lattice_circuit(5, 5, 10, seed + j, "haar", "cz", f"mix5x5d10_{j}"), 0))
+        pool.append(("6x6d12", lattice_circuit(6, 6, 12, seed + 10 + j, "haar", "cz", f"mix6x6d12_{j}"), 0))
+        pool.append(("8x8d16", lattice_circuit(8, 8, 16, seed + 20 + j, "haar", "cz", f"mix8x8d16_{j}"), 10))
+        pool.append(("3x3x4", stack3d_circuit(3, 3, 4, 10, seed + 30 + j, f"mix3x3x4_{j}"), 0))
     return pool

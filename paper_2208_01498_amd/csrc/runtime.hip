@@ -79,7 +79,7 @@ static void fill_perm(PermArgs& pa, const int* map, int r) {
 // as a slice block (2^r slices per pass), `chunk` bitstrings per pass.  The
 // largest block that fits with at least one bitstring is taken (a forced r
 // from the context option wins when it fits), then the largest chunk.
-static bool choose_shape(const tn_plan* plan, int nb, size_t ws_bytes, int force_r, int& r_out,
+bool choose_shape(const tn_plan* plan, int nb, size_t ws_bytes, int force_r, int& r_out,
                          int& chunk_out) {
     tn_plan* pl = const_cast<tn_plan*>(plan);
     const int S = (int)plan->host.sliced.size();
@@ -100,12 +100,15 @@ static bool choose_shape(const tn_plan* plan, int nb, size_t ws_bytes, int force
 }
 
 int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int precision,
-            hipStream_t stream, char* ws, size_t ws_bytes, double* out, tn_exec_stats* stats) {
+            hipStream_t stream, char* ws, size_t ws_bytes, double* out, tn_exec_stats* stats,
+            int shape_r, int shape_chunk) {
     const PlanHost& p = plan->host;
     tn_plan* pl = const_cast<tn_plan*>(plan);
     tn_exec_stats es{};
-    int r = 0, chunk = 0;
-    if (!choose_shape(plan, nb, ws_bytes, ctx ? ctx->force_slice_block : -1, r, chunk)) {
+    int r = shape_r, chunk = shape_chunk;
+    if (shape_chunk > 0 && pl->mem(shape_chunk, shape_r).bytes <= ws_bytes) {
+        // shape fixed by the caller (the serving loop reserved its memory)
+    } else if (!choose_shape(plan, nb, ws_bytes, ctx ? ctx->force_slice_block : -1, r, chunk)) {
         set_error("one bitstring of this plan needs more workspace than available");
         return TN_ENOMEM;
     }

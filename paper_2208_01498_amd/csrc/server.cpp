@@ -61,6 +61,7 @@ static void worker(tn_ctx* ctx, Slot* sl) {
         const tn_plan* plan = sl->plan;
         int prec = sl->precision;
         size_t off = sl->off, bytes = sl->bytes;
+        const int sr = sl->shape_r, sc = sl->shape_chunk;
         lk.unlock();
         std::vector<uint64_t> bits;
         for (auto& r : job) bits.insert(bits.end(), r->bits.begin(), r->bits.end());
@@ -68,7 +69,7 @@ static void worker(tn_ctx* ctx, Slot* sl) {
         int64_t t0 = now_ns();
         for (auto& r : job) r->st.t_start_ns = t0;
         int rc = execute(ctx, plan, bits.data(), (int)bits.size(), prec, sl->stream,
-                         ctx->arena + off, bytes, res.data(), nullptr);
+                         ctx->arena + off, bytes, res.data(), nullptr, sr, sc);
         int64_t t1 = now_ns();
         lk.lock();
         size_t pos = 0;
@@ -151,13 +152,14 @@ static void scheduler(tn_ctx* ctx) {
             ctx->scv.wait(lk);
             continue;
         }
-        int lo = 1, hi = total;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) / 2;
-            if (plan->mem(mid, 0).bytes <= avail) lo = mid;
-            else hi = mid - 1;
-        }
-        size_t bytes = plan->mem(lo, 0).bytes;
+        // execution shape for the largest free region; reserve exactly its
+        // workspace (the batch then runs in that shape)
+        // one batch takes at most half of the arena when it can run in less,
+        // so that other requests keep being admitted beside it
+        int r = 0, ch = 0;
+        size_t cap = std::max(need1, std::min(avail, ctx->arena_bytes / 2));
+        choose_shape(plan, total, cap, ctx->force_slice_block, r, ch);
+        size_t bytes = plan->mem(ch, r).bytes;
         size_t off = 0;
         arena_alloc(ctx, bytes, &off);
         int64_t t = now_ns();
@@ -168,6 +170,8 @@ static void scheduler(tn_ctx* ctx) {
         slot->precision = head->precision;
         slot->off = off;
         slot->bytes = bytes;
+        slot->shape_r = r;
+        slot->shape_chunk = ch;
         slot->has_job = true;
         slot->cv.notify_all();
     }

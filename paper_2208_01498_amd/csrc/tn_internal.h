@@ -146,6 +146,7 @@ struct Slot {
     const tn_plan* plan = nullptr;
     int precision = 0;
     size_t off = 0, bytes = 0;
+    int shape_r = 0, shape_chunk = 0;
     std::condition_variable cv;
 };
 
@@ -186,7 +187,9 @@ namespace tn {
 // workspace [ws, ws + ws_bytes).  Blocking iff sync.
 int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb,
             int precision, hipStream_t stream, char* ws, size_t ws_bytes,
-            double* out, tn_exec_stats* stats);
+            double* out, tn_exec_stats* stats, int shape_r = 0, int shape_chunk = 0);
+// execution shape (log2 slices per pass, bitstrings per pass) for a workspace
+bool choose_shape(const tn_plan* plan, int nb, size_t ws_bytes, int force_r, int& r, int& chunk);
 int64_t now_ns();
 // arena sub-allocation (callers hold ctx->smu)
 bool arena_alloc(tn_ctx* ctx, size_t bytes, size_t* off);

@@ -1,0 +1,123 @@
+"""Serving loop: continuous batching through tn_submit / tn_poll."""
+import time
+
+import numpy as np
+import pytest
+
+from circuits import lattice_circuit, stack3d_circuit, random_bitstrings
+from oracle import statevector_amplitudes
+
+pytestmark = pytest.mark.gpu
+
+
+def _plans():
+    from paper_2208_01498_amd.planner.plan import make_plan
+    circs = [lattice_circuit(4, 4, 8, 601, "haar", "cz"),
+             lattice_circuit(3, 5, 10, 602, "sqrt", "fsim"),
+             stack3d_circuit(2, 2, 4, 8, 603),
+             lattice_circuit(4, 5, 12, 604, "haar", "cz")]
+    return circs, [make_plan(c, n_slices=ns, B=16) for c, ns in zip(circs, (2, 0, 0, 4))]
+
+
+def _wait(B, ctx, tickets, sizes, timeout=60.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t, n in zip(tickets, sizes):
+            if t in out:
+                continue
+            r = B.tn_poll(ctx, t, n)
+            if r is not None:
+                out[t] = r
+        assert time.time() - t0 < timeout, "served requests did not finish"
+        time.sleep(0.002)
+    return out
+
+
+def test_mixed_stream_equals_alone_runs():
+    """Requests on four plans, batch sizes 1..16, submitted together: each
+    result is bitwise the alone-run result and matches the state vector."""
+    from paper_2208_01498_amd import binding as B
+    circs, plans = _plans()
+    eng = B.Engine(0, arena_bytes=512 << 20)
+    try:
+        B.tn_server_config(eng.ctx, 3, 32)
+        hs = [eng.load(p.to_blob()) for p in plans]
+        rng = np.random.Generator(np.random.PCG64(610))
+        reqs = []
+        for i in range(24):
+            k = int(rng.integers(len(plans)))
+            nb = int(rng.integers(1, 17))
+            words = random_bitstrings(circs[k].n, nb, 700 + i)
+            reqs.append((k, words))
+        alone = [eng.amplitudes(hs[k], w, 0) for k, w in reqs]
+        print("submitting", len(reqs), "requests", flush=True)
+        tickets = [B.tn_submit(eng.ctx, hs[k], w, 0) for k, w in reqs]
+        res = _wait(B, eng.ctx, tickets, [len(w) for _, w in reqs])
+        merged = 0
+        for (k, w), t, a in zip(reqs, tickets, alone):
+            amps, st = res[t]
+            assert np.array_equal(amps, a)
+            assert st["t_arrive_ns"] <= st["t_admit_ns"] <= st["t_start_ns"] <= st["t_end_ns"]
+            merged += st["batch"] > len(w)
+        print("requests served inside a merged batch:", merged, flush=True)
+        for (k, w), a in zip(reqs[:6], alone[:6]):
+            ref = statevector_amplitudes(circs[k], w)
+            err = np.abs(a - ref) / np.maximum(np.abs(ref), 2.0 ** (-circs[k].n / 2))
+            assert err.max() <= 1e-5
+    finally:
+        eng.close()
+
+
+def test_cancel_poll_and_unload_busy():
+    from paper_2208_01498_amd import binding as B
+    circs, plans = _plans()
+    eng = B.Engine(0, arena_bytes=256 << 20)
+    try:
+        B.tn_server_config(eng.ctx, 1, 16)
+        h = eng.load(plans[3].to_blob())
+        words = random_bitstrings(circs[3].n, 16, 801)
+        ts = [B.tn_submit(eng.ctx, h, words, 0) for _ in range(6)]
+        B.tn_cancel(eng.ctx, ts[-1])
+        with pytest.raises(B.TnError) as e:
+            B.tn_plan_unload(eng.ctx, h)
+        assert e.value.code in (B.TN_EBUSY,)
+        got = {}
+        t0 = time.time()
+        while len(got) < len(ts):
+            for t in ts:
+                if t in got:
+                    continue
+                try:
+                    r = B.tn_poll(eng.ctx, t, 16)
+                except B.TnError as err:
+                    got[t] = err.code
+                    continue
+                if r is not None:
+                    got[t] = r
+            assert time.time() - t0 < 60
+            time.sleep(0.002)
+        assert got[ts[-1]] == B.TN_ECANCELLED
+        assert all(not isinstance(got[t], int) for t in ts[:-1])
+        with pytest.raises(B.TnError) as e:
+            B.tn_poll(eng.ctx, ts[0], 16)
+        assert e.value.code == B.TN_ENOTFOUND
+    finally:
+        eng.close()
+
+
+def test_submit_rejects_requests_that_never_fit():
+    from paper_2208_01498_amd import binding as B
+    circs, plans = _plans()
+    info = B.tn_plan_validate(plans[3].to_blob())
+    need = info["peak_bytes_fixed"] + info["peak_bytes_per_b"]
+    eng = B.Engine(0, arena_bytes=max(1 << 20, need // 4) if need // 4 >= (1 << 20) else 1 << 20)
+    try:
+        h = eng.load(plans[3].to_blob())
+        if need <= (1 << 20):
+            pytest.skip("plan workspace fits the minimum arena")
+        with pytest.raises(B.TnError) as e:
+            B.tn_submit(eng.ctx, h, random_bitstrings(circs[3].n, 2, 811), 0)
+        assert e.value.code == B.TN_ENOMEM
+    finally:
+        eng.close()

@@ -41,7 +41,7 @@ def test_gate_unitarity_all_generators():
     for name in ("cfg1", "cfg2", "cfg3", "cfg4"):
         c, _, _ = make_config(name)
         mats += [g.matrix for g in c.gates]
-    for _, c in serving_pool():
+    for _, c, _ in serving_pool():
         mats += [g.matrix for g in c.gates]
     for m in mats:
         assert np.max(np.abs(m.conj().T @ m - np.eye(m.shape[0]))) <= 1e-14
