@@ -33,7 +33,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
-constexpr int KT = 16;
+constexpr int KT_SPLIT = 16;   // complex k per LDS stage, split bf16 (two MFMA k-steps)
+constexpr int KT_FP32 = 8;     // complex k per LDS stage, FP32 (keeps two workgroups per CU)
+constexpr int KT = 16;         // K granularity of the split-K ranges
 
 // bits of x at the set positions of m, compacted (parallel bit extract)
 __device__ __forceinline__ size_t pext_u(size_t x, unsigned m) {
@@ -51,14 +53,17 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
 
 template <int PREC, int WGM, int WGN, int WMF, int WNF>
 struct Smem {
+    static constexpr int KT = PREC == 0 ? KT_FP32 : KT_SPLIT;
     static constexpr int BM = WGM * 32 * WMF;
     static constexpr int BN = WGN * 16 * WNF;
-    // FP32: A as [k][m], B as [k][n] (complex), padded rows
+    // FP32: A as [k][m] complex; B as [k][n] with each complex stored as the
+    // four reals (Br, Bi, -Bi, Br) of its 2 x 2 real block, so every lane
+    // reads its MFMA operand with one 4-byte load and no select
     static constexpr int PA = BM + 2;
-    static constexpr int PB = BN + 2;
+    static constexpr int PB = BN + 1;            // in 16-byte units
     // bf16: A as [m][2*KT real], B as [2*BN real cols][2*KT real rows]
     static constexpr int RA = 2 * KT + 8;
-    static constexpr size_t bytes_fp32 = 2 * (size_t)KT * (PA + PB) * sizeof(float2);
+    static constexpr size_t bytes_fp32 = 2 * (size_t)KT * (PA * 8 + PB * 16);
     static constexpr size_t bytes_bf16 = 2 * (size_t)(2 * BM * RA + 2 * 2 * BN * RA) * 2;
     static constexpr size_t bytes = PREC == 0 ? bytes_fp32 : bytes_bf16;
 };
@@ -68,6 +73,7 @@ struct Smem {
 template <int PREC, int WGM, int WGN, int WMF, int WNF, bool TA, bool TB>
 __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
     using S = Smem<PREC, WGM, WGN, WMF, WNF>;
+    constexpr int KT = S::KT;
     constexpr int NT = 64 * WGM * WGN;
     constexpr int BM = S::BM, BN = S::BN, PA = S::PA, PB = S::PB, RA = S::RA;
     constexpr int FA = BM * KT / 2;      // float4 (2 complex) loads per A tile
@@ -187,12 +193,21 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
 
     // ---------------------------------------------------------------- FP32
     float2* As = reinterpret_cast<float2*>(smem);              // [2][KT][PA]
-    float2* Bs = As + 2 * KT * PA;                              // [2][KT][PB]
+    float4* Bs = reinterpret_cast<float4*>(As + 2 * KT * PA);  // [2][KT][PB]
     // ---------------------------------------------------------------- bf16
     __bf16* Ah = reinterpret_cast<__bf16*>(smem);               // [2][BM][RA]
     __bf16* Al = Ah + 2 * BM * RA;
     __bf16* Bh = Al + 2 * BM * RA;                               // [2][2BN][RA]
     __bf16* Bl = Bh + 2 * 2 * BN * RA;
+
+    // two floats -> packed bf16 pairs (hi, lo) with x = hi + lo
+    auto split2 = [](float a, float b, uint32_t& hi, uint32_t& lo) {
+        __bf16 ha, la, hb, lb;
+        split_bf16(a, ha, la);
+        split_bf16(b, hb, lb);
+        hi = (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+        lo = (uint32_t)__builtin_bit_cast(uint16_t, la) | ((uint32_t)__builtin_bit_cast(uint16_t, lb) << 16);
+    };
 
     auto store = [&](int buf) {
 #pragma unroll
@@ -202,19 +217,22 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
             int m, k, m2, k2;   // element 0 at (m,k), element 1 at (m2,k2)
             if (!TA) { m = f / (KT / 2); k = 2 * (f % (KT / 2)); m2 = m; k2 = k + 1; }
             else { k = f / (BM / 2); m = 2 * (f % (BM / 2)); m2 = m + 1; k2 = k; }
-            const float2 x = make_float2(ra[i].x, ra[i].y), y = make_float2(ra[i].z, ra[i].w);
             if constexpr (PREC == 0) {
                 float2* a = As + buf * KT * PA;
                 if (TA) *reinterpret_cast<float4*>(a + k * PA + m) = ra[i];
-                else { a[k * PA + m] = x; a[k2 * PA + m2] = y; }
+                else {
+                    a[k * PA + m] = make_float2(ra[i].x, ra[i].y);
+                    a[k2 * PA + m2] = make_float2(ra[i].z, ra[i].w);
+                }
             } else {
-                __bf16* ah = Ah + buf * BM * RA;
-                __bf16* al = Al + buf * BM * RA;
-                __bf16 h, l;
-                split_bf16(x.x, h, l); ah[m * RA + 2 * k] = h; al[m * RA + 2 * k] = l;
-                split_bf16(x.y, h, l); ah[m * RA + 2 * k + 1] = h; al[m * RA + 2 * k + 1] = l;
-                split_bf16(y.x, h, l); ah[m2 * RA + 2 * k2] = h; al[m2 * RA + 2 * k2] = l;
-                split_bf16(y.y, h, l); ah[m2 * RA + 2 * k2 + 1] = h; al[m2 * RA + 2 * k2 + 1] = l;
+                uint32_t* ah = reinterpret_cast<uint32_t*>(Ah + buf * BM * RA);
+                uint32_t* al = reinterpret_cast<uint32_t*>(Al + buf * BM * RA);
+                uint32_t h0, l0, h1, l1;
+                split2(ra[i].x, ra[i].y, h0, l0);
+                split2(ra[i].z, ra[i].w, h1, l1);
+                // real index 2k + (re, im) of row m: one 4-byte word per complex
+                ah[(m * RA + 2 * k) / 2] = h0; al[(m * RA + 2 * k) / 2] = l0;
+                ah[(m2 * RA + 2 * k2) / 2] = h1; al[(m2 * RA + 2 * k2) / 2] = l1;
             }
         }
 #pragma unroll
@@ -224,49 +242,42 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
             int k, n, k2, n2;
             if (!TB) { k = f / (BN / 2); n = 2 * (f % (BN / 2)); k2 = k; n2 = n + 1; }
             else { n = f / (KT / 2); k = 2 * (f % (KT / 2)); n2 = n; k2 = k + 1; }
-            const float2 x = make_float2(rb[i].x, rb[i].y), y = make_float2(rb[i].z, rb[i].w);
             if constexpr (PREC == 0) {
-                float2* b = Bs + buf * KT * PB;
-                if (!TB) *reinterpret_cast<float4*>(b + k * PB + n) = rb[i];
-                else { b[k * PB + n] = x; b[k2 * PB + n2] = y; }
+                float4* b = Bs + buf * KT * PB;
+                b[k * PB + n] = make_float4(rb[i].x, rb[i].y, -rb[i].y, rb[i].x);
+                b[k2 * PB + n2] = make_float4(rb[i].z, rb[i].w, -rb[i].w, rb[i].z);
             } else {
-                __bf16* bh = Bh + buf * 2 * BN * RA;
-                __bf16* bl = Bl + buf * 2 * BN * RA;
-                auto put = [&](int kk, int nn, float2 v) {
-                    // real column 2n: rows (2k, 2k+1) = (Br, -Bi); column 2n+1: (Bi, Br)
-                    __bf16 h, l;
-                    split_bf16(v.x, h, l);
-                    bh[(2 * nn) * RA + 2 * kk] = h; bl[(2 * nn) * RA + 2 * kk] = l;
-                    bh[(2 * nn + 1) * RA + 2 * kk + 1] = h; bl[(2 * nn + 1) * RA + 2 * kk + 1] = l;
-                    split_bf16(-v.y, h, l);
-                    bh[(2 * nn) * RA + 2 * kk + 1] = h; bl[(2 * nn) * RA + 2 * kk + 1] = l;
-                    split_bf16(v.y, h, l);
-                    bh[(2 * nn + 1) * RA + 2 * kk] = h; bl[(2 * nn + 1) * RA + 2 * kk] = l;
-                };
-                put(k, n, x);
-                put(k2, n2, y);
+                uint32_t* bh = reinterpret_cast<uint32_t*>(Bh + buf * 2 * BN * RA);
+                uint32_t* bl = reinterpret_cast<uint32_t*>(Bl + buf * 2 * BN * RA);
+                // real column 2n: rows (2k, 2k+1) = (Br, -Bi); column 2n+1: (Bi, Br)
+                uint32_t h, l;
+                split2(rb[i].x, -rb[i].y, h, l);
+                bh[((2 * n) * RA + 2 * k) / 2] = h; bl[((2 * n) * RA + 2 * k) / 2] = l;
+                split2(rb[i].y, rb[i].x, h, l);
+                bh[((2 * n + 1) * RA + 2 * k) / 2] = h; bl[((2 * n + 1) * RA + 2 * k) / 2] = l;
+                split2(rb[i].z, -rb[i].w, h, l);
+                bh[((2 * n2) * RA + 2 * k2) / 2] = h; bl[((2 * n2) * RA + 2 * k2) / 2] = l;
+                split2(rb[i].w, rb[i].z, h, l);
+                bh[((2 * n2 + 1) * RA + 2 * k2) / 2] = h; bl[((2 * n2 + 1) * RA + 2 * k2) / 2] = l;
             }
         }
     };
 
     auto compute = [&](int buf) {
         if constexpr (PREC == 0) {
-            const float2* a = As + buf * KT * PA;
-            const float2* b = Bs + buf * KT * PB;
+            // lane (half, l32): A real row l32 col half = (re, im)[half] of
+            // A[m][k]; B real row half, col l32 = entry 2*half + (l32 & 1) of
+            // the expanded 2 x 2 block of B[k][n = l32/2]
+            const float* a = reinterpret_cast<const float*>(As + buf * KT * PA);
+            const float* b = reinterpret_cast<const float*>(Bs + buf * KT * PB);
+            const int boff = 4 * (l32 >> 1) + 2 * half + (l32 & 1);
 #pragma unroll
             for (int kk = 0; kk < KT; ++kk) {
                 float av[WMF], bv[WNF];
 #pragma unroll
-                for (int i = 0; i < WMF; ++i) {
-                    const float2 x = a[kk * PA + wm + i * 32 + l32];
-                    av[i] = half ? x.y : x.x;
-                }
+                for (int i = 0; i < WMF; ++i) av[i] = a[2 * (kk * PA + wm + i * 32 + l32) + half];
 #pragma unroll
-                for (int j = 0; j < WNF; ++j) {
-                    const float2 y = b[kk * PB + wn + j * 16 + (l32 >> 1)];
-                    const int c = l32 & 1;
-                    bv[j] = half ? (c ? y.x : -y.y) : (c ? y.y : y.x);
-                }
+                for (int j = 0; j < WNF; ++j) bv[j] = b[4 * (kk * PB + wn + j * 16) + boff];
 #pragma unroll
                 for (int i = 0; i < WMF; ++i)
 #pragma unroll
