@@ -36,7 +36,7 @@ def cpu_baseline(circ, word, seconds=20.0, width=24, seed=0):
     import numpy as np
     from oracle.pairwise import OracleNetwork, _restrict, _evaluate
     from paper_2208_01498_amd.planner.plan import make_plan
-    plan = make_plan(circ, n_slices=None, target_width=width, B=1, seed=seed)
+    plan = make_plan(circ, n_slices=None, target_width=width, B=1, seed=seed, objective="oracle")
     spec = plan.order_spec()
     net = OracleNetwork(circ, word)
     labels = net.labels_of_slice_spec(spec["sliced"])

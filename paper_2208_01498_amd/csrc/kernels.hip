@@ -46,38 +46,69 @@ __global__ void k_gather_leaf(GatherArgs g) {
 
 // ---------------------------------------------------------------------------
 // One workgroup per tile: the tile holds every combination of the tile bits
-// T (the lowest input bits plus the input bits that become the lowest
-// output bits) for fixed values of all other bits and of b.
+// T (the lowest input bits plus the input bits that become the lowest output
+// bits) for fixed values of all other bits and of b.  Tile bit 0 is input bit
+// 0 and, in output order, output bit 0, so elements move in adjacent pairs:
+// 16-byte reads along the lowest input bits, 16-byte writes along the lowest
+// output bits.  Tile bits 1..8 (input order for the reads, output order for
+// the writes) are the thread id, deposited once per thread.  The LDS index
+// keeps bit 0 and XORs bits 5..8 into bits 1..4, so the strided reads of the
+// write phase spread over the banks.
+__device__ __forceinline__ unsigned swz(unsigned e) { return e ^ (((e >> 5) & 15u) << 1); }
+
 __global__ void __launch_bounds__(256) k_permute_tiled(PermArgs a) {
     extern __shared__ float2 lds[];
     const int t = a.nt;
-    const size_t tile_elems = size_t(1) << t;
     const size_t r_elems = size_t(1) << a.rank;
-    const size_t tid = blockIdx.x;
+    const size_t tid_blk = blockIdx.x;
     const size_t b = blockIdx.y;
     size_t base_in = 0, base_out = 0;
     for (int m = 0; m < a.nn; ++m)
-        if ((tid >> m) & 1) {
+        if ((tid_blk >> m) & 1) {
             base_in |= size_t(1) << a.n_in[m];
             base_out |= size_t(1) << a.n_out[m];
         }
     const float2* src = a.src + b * r_elems + base_in;
     float2* dst = a.dst + b * r_elems + base_out;
-    for (size_t e = threadIdx.x; e < tile_elems; e += blockDim.x) {
-        size_t off = 0;
-        for (int m = 0; m < t; ++m)
-            if ((e >> m) & 1) off |= size_t(1) << a.t_in[m];
-        lds[e + (e >> 5)] = src[off];
+    const unsigned th = threadIdx.x;
+    if (t == 0) {
+        if (th == 0) dst[0] = src[0];
+        return;
+    }
+    const int tp = t - 1;                         // pair-index bits
+    const int tl = tp < 8 ? tp : 8;               // carried by the thread id
+    const unsigned iters = 1u << (tp - tl);
+    if (th >= (1u << tl)) {
+        __syncthreads();
+        return;
+    }
+    size_t in_lo = 0, out_lo = 0;
+    unsigned e_lo = 0;
+    for (int m = 0; m < tl; ++m)
+        if ((th >> m) & 1) {
+            in_lo |= size_t(1) << a.t_in[m + 1];
+            out_lo |= size_t(1) << a.t_out[m + 1];
+            e_lo |= 1u << a.t_rank[m + 1];
+        }
+    const unsigned e_bit0 = 1u << a.t_rank[0];    // input tile index of output bit 0
+    for (unsigned k = 0; k < iters; ++k) {
+        size_t off = in_lo;
+        for (int m = tl; m < tp; ++m)
+            if ((k >> (m - tl)) & 1) off |= size_t(1) << a.t_in[m + 1];
+        const float4 v = *reinterpret_cast<const float4*>(src + off);
+        *reinterpret_cast<float4*>(&lds[swz((((k << tl) | th) << 1))]) = v;
     }
     __syncthreads();
-    for (size_t f = threadIdx.x; f < tile_elems; f += blockDim.x) {
-        size_t off = 0, e = 0;
-        for (int m = 0; m < t; ++m)
-            if ((f >> m) & 1) {
-                off |= size_t(1) << a.t_out[m];
-                e |= size_t(1) << a.t_rank[m];
+    for (unsigned k = 0; k < iters; ++k) {
+        size_t off = out_lo;
+        unsigned e = e_lo;
+        for (int m = tl; m < tp; ++m)
+            if ((k >> (m - tl)) & 1) {
+                off |= size_t(1) << a.t_out[m + 1];
+                e |= 1u << a.t_rank[m + 1];
             }
-        dst[off] = lds[e + (e >> 5)];
+        const float2 x = lds[swz(e)], y = lds[swz(e | e_bit0)];
+        *reinterpret_cast<float4*>(dst + off) = make_float4(x.x, x.y, y.x, y.y);
     }
 }
 
@@ -123,8 +154,10 @@ hipError_t launch_gather(const GatherArgs& g, hipStream_t s) {
 hipError_t launch_permute(const PermArgs& a, hipStream_t s) {
     size_t tiles = size_t(1) << a.nn;
     size_t tile_elems = size_t(1) << a.nt;
-    size_t lds = (tile_elems + (tile_elems >> 5)) * sizeof(float2);
-    int threads = tile_elems >= 256 ? 256 : (int)((tile_elems + 63) / 64 * 64);
+    // the swizzle moves an index within its 1024-element block
+    size_t lds = (tile_elems < 1024 ? 1024 : tile_elems) * sizeof(float2);
+    int threads = tile_elems >= 512 ? 256 : (int)((tile_elems / 2 + 63) / 64 * 64);
+    if (threads < 64) threads = 64;
     hipLaunchKernelGGL(k_permute_tiled, dim3((unsigned)tiles, (unsigned)a.nb), dim3(threads), lds, s, a);
     return hipGetLastError();
 }

@@ -41,7 +41,7 @@ int64_t now_ns() {
 static void fill_perm(PermArgs& pa, const int* map, int r) {
     int inv[kMaxRank];
     for (int p = 0; p < r; ++p) inv[map[p]] = p;
-    const int target = std::min(r, 10);
+    const int target = std::min(r, 12);
     std::vector<char> inT(r, 0);
     int a = 0, c = 0, t = 0;
     auto add = [&](int q) { if (!inT[q]) { inT[q] = 1; ++t; } };

@@ -158,7 +158,10 @@ def build_network(circ, simplify=True, swap_relabel=False, coarsen=0):
                                   set(), circ.positions[q]))
             labels[lid].kind = "out"
         else:
+            # after wire exchanges the last label of qubit q may have been
+            # started on another qubit: it is measured on q
             labels[cur[q]].kind = "out"
+            labels[cur[q]].qubit = q
     net = Network(n, labels, factors, scale, circ.positions)
     if simplify:
         simplify_network(net)

@@ -103,7 +103,10 @@ class SliceModel:
             ub = sum(self.bits[l] for l in u if l not in Sset)
             cb = sum(self.bits[l] for l in lc if l not in Sset)
             f = 8.0 * 2.0 ** ub * bsz
-            if self.blocked:
+            if self.objective == "oracle":
+                # every step of every slice, no reuse (the CPU oracle)
+                reps = 2.0 ** nS
+            elif self.blocked:
                 # all slices in one pass: one copy per value of the sliced
                 # labels in the step's subtree
                 reps = 2.0 ** len(hit)

@@ -147,3 +147,54 @@ def test_plan_blob_accepted_by_library_validator():
         info = B.tn_plan_validate(plan.to_blob())
         assert info["n_steps"] == info["n_leaves"] - 1
         assert info["n_sliced"] == len(plan.sliced)
+
+
+def _contract_plan_network(plan, word):
+    """Dense FP64 contraction of the planner's own factors in the plan's
+    order (test helper): output labels fixed to the bitstring, sliced labels
+    summed by the contraction itself."""
+    from oracle.pairwise import contract_pair
+    net = plan.net
+    live = {}
+    for i, f in enumerate(net.factors):
+        d, ls = f.data, list(f.labels)
+        idx = tuple(((int(word) >> net.labels[l].qubit) & 1) if net.labels[l].kind == "out"
+                    else slice(None) for l in ls)
+        live[i] = (d[idx], [l for l in ls if net.labels[l].kind != "out"])
+    nid = len(net.factors)
+    for a, b in plan.steps:
+        A, la = live.pop(a)
+        B, lb = live.pop(b)
+        others = set(l for _, ls in live.values() for l in ls)
+        keep = set(l for l in set(la) | set(lb) if l in others)
+        live[nid] = contract_pair(A, la, B, lb, keep)
+        nid += 1
+    (arr, ls), = live.values()
+    return complex(np.asarray(arr).sum()) * net.scale
+
+
+@pytest.mark.parametrize("name,mk", CIRCS, ids=[c[0] for c in CIRCS])
+def test_plan_network_matches_statevector(name, mk):
+    """The planner's network itself (diagonal hyperedges, wire exchanges,
+    absorbed gates, structural zeros) contracted on the host equals the
+    state vector."""
+    circ = mk()
+    words = random_bitstrings(circ.n, 3, 430)
+    plan = make_plan(circ, n_slices=0, B=3)
+    got = np.array([_contract_plan_network(plan, w) for w in words])
+    ref = statevector_amplitudes(circ, words)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_swap_form_network_matches_statevector():
+    from paper_2208_01498_amd.planner.network import build_network
+    from paper_2208_01498_amd.planner.plan import Plan
+    circ = lattice_circuit(3, 3, 5, 440, "sqrt", "fsim")
+    words = random_bitstrings(circ.n, 3, 441)
+    net = build_network(circ, swap_relabel=True)
+    tb = TreeBuilder(net, np.random.Generator(np.random.PCG64(0)), bottom=8)
+    steps = tree_steps(tb.build(), len(net.factors))
+    plan = Plan(circ, net, steps, [], None, None, None, None)
+    got = np.array([_contract_plan_network(plan, w) for w in words])
+    ref = statevector_amplitudes(circ, words)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
