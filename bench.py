@@ -21,7 +21,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32": 157.3e12, "bf16x3": 2516.6e12}
+PEAK = {"fp32": 157.3e12, "fp32_3m": 157.3e12, "bf16x3": 2516.6e12}
+# executed MFMA flops per algorithmic flop (8 real flops per complex
+# multiply-add): 4M executes exactly those, 3M three real products instead
+# of four, split bf16 three 16-bit products of the 4M form
+EXEC = {"fp32": 1.0, "fp32_3m": 0.75, "bf16x3": 3.0}
 
 # HBM traffic per launch of a kernel class, from two rocprofv3 --pmc passes
 # (FETCH_SIZE, WRITE_SIZE) over `bench.py --batch 3 --warmup 0 --steps 1
@@ -106,6 +110,7 @@ def serve_bench(args):
     from paper_2208_01498_amd.planner.plan import make_plan
     from paper_2208_01498_amd import binding as B
     pool = serving_pool()
+    prec = B.PRECISIONS[args.precision]
     t = time.perf_counter()
     plans = [make_plan(c, n_slices=ns, B=32) for _, c, ns in pool]
     log("12 plans built in %.1f s" % (time.perf_counter() - t))
@@ -132,7 +137,7 @@ def serve_bench(args):
             now = time.perf_counter() - t0
             while i < len(reqs) and arrivals[i] <= now:
                 k, w = reqs[i]
-                pending[B.tn_submit(eng.ctx, hs[k], w, 0)] = (i, len(w))
+                pending[B.tn_submit(eng.ctx, hs[k], w, prec)] = (i, len(w))
                 i += 1
             for tk in list(pending):
                 j, n = pending[tk]
@@ -162,7 +167,7 @@ def serve_bench(args):
     same = True
     for j in range(min(6, len(reqs))):
         k, w = reqs[j]
-        same &= bool(np.array_equal(eng.amplitudes(hs[k], w, 0), done[j][0]))
+        same &= bool(np.array_equal(eng.amplitudes(hs[k], w, prec), done[j][0]))
     per_fam = {}
     for j, (k, w) in enumerate(reqs):
         per_fam.setdefault(pool[k][0], []).append(lat[j])
@@ -170,7 +175,7 @@ def serve_bench(args):
            "p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
            "req_per_s": len(reqs) / el, "amplitudes_per_s": amps / el,
            "lambda_req_per_s": lam, "saturation_req_per_s": sat, "n_requests": len(reqs),
-           "slots": args.slots, "alone_equals_mixed": same,
+           "slots": args.slots, "alone_equals_mixed": same, "precision": args.precision,
            "p50_by_family": {f: float(np.percentile(v, 50)) for f, v in per_fam.items()},
            "config": {"workload": "served mix: 5x5 d10, 6x6 d12, 8x8 d16 (2^10 slices) "
                                   "Haar SU(2)+CZ lattices and 3x3x4 SU(4) stack, "
@@ -186,7 +191,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="cfg3")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_3m", "bf16x3"])
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--slices", type=int, default=10)
     ap.add_argument("--width", type=float, default=None)
@@ -258,12 +263,14 @@ def main():
     log("per kernel class", json.dumps(per_kind))
     dom = max(range(4), key=lambda i: prof["time_ms"][i])
     ms = prof["time_ms"][dom]
-    achieved = prof["flops"][dom] / (ms * 1e-3) if ms > 0 else 0.0
+    alg = prof["flops"][dom] / (ms * 1e-3) if ms > 0 else 0.0
+    achieved = alg * EXEC[args.precision]
     peak = PEAK[args.precision]
     roofline = {"bound": "mfma", "kernel": kinds[dom],
                 "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None,
-                "flops_per_launch": prof["flops"][dom] / max(1, prof["launches"][dom]),
+                "flops_per_launch": prof["flops"][dom] * EXEC[args.precision] / max(1, prof["launches"][dom]),
+                "algorithmic_tflops": alg / 1e12,
                 "avg_launch_ms": ms / max(1, prof["launches"][dom]),
                 "gemm_time_frac": sum(prof["time_ms"][:4]) / max(1e-9, sum(prof["time_ms"]))}
     rec = TRAFFIC.get(kinds[dom])
@@ -278,7 +285,8 @@ def main():
         "value": value, "unit": "amplitudes/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64/f32-mfma" if args.precision == "fp32" else "bf16x3-mfma/f32-acc",
+        "dtype": {"fp32": "c64/f32-mfma", "fp32_3m": "c64/f32-mfma-3m",
+                  "bf16x3": "bf16x3-mfma/f32-acc"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (args.config, info["desc"]), "batch": nb,
                    "slices": 1 << len(plan.sliced), "precision": args.precision,

@@ -48,9 +48,12 @@ extern "C" {
 
 /* precision modes */
 #define TN_FP32_4M 0        /* complex64 operands, 4 real products, FP32 MFMA   */
-#define TN_FP32_3M 1        /* complex64 operands, 3 real products (Gauss)      */
+#define TN_FP32_3M 1        /* complex64 operands, 3 real products on FP32 MFMA:
+                               Ar Br, Ai Bi, (Ar+Ai)(Br+Bi); steps whose output
+                               has at most 16 entries use the 4M dot kernel */
 #define TN_SPLIT_BF16 2     /* x = hi + lo in bf16, hi*hi + hi*lo + lo*hi, FP32 acc */
-#define TN_SPLIT_FP16 3     /* same with fp16 halves and power-of-two scaling   */
+#define TN_SPLIT_FP16 3     /* reserved: fp16 halves with power-of-two scaling;
+                               rejected with TN_EINVAL */
 
 typedef struct tn_ctx tn_ctx;
 typedef struct tn_plan tn_plan;
@@ -194,7 +197,7 @@ int tn_last_exec_stats(tn_ctx* ctx, tn_exec_stats* out);
  *   A(m,k) = A[ob*sAb + ib*sAi + (transA ? k*M + m : m*K + k)]
  *   B(k,n) = B[ob*sBb + ib*sBi + (transB ? n*K + k : k*N + n)]
  *   strides in complex elements; sAb or sBb may be 0 (broadcast); M, N, K
- *   powers of two.  precision TN_FP32_4M or TN_SPLIT_BF16.  `scratch`:
+ *   powers of two.  precision TN_FP32_4M, TN_FP32_3M or TN_SPLIT_BF16.  `scratch`:
  *   device memory for split-K partial sums (see
  *   tn_kernel_cgemm_scratch_bytes).  Returns TN_EINVAL for bad sizes or too
  *   little scratch, TN_EDEVICE on a launch error.

@@ -12,7 +12,11 @@
 //                   split x = hi + lo when staged into LDS, and
 //                   hi*hi + hi*lo + lo*hi are accumulated in FP32; one MFMA is
 //                   32 x 16 x 8 (complex)
-//   k_cgemm_dot     tiny M*N with long K: a K-parallel dot product
+//   k_cgemm3m       FP32 3M on the same MFMA used as a real 32 x 32 x 2
+//                   product: three real products per complex product
+//                   (6 MNK executed flops instead of 8 MNK)
+//   k_cgemm_dot     tiny M*N with long K: a K-parallel dot product (every
+//                   precision mode)
 //   split-K         when a shape has too few output tiles to fill the chip,
 //                   K is cut into a fixed number of ranges whose partial
 //                   products are summed in range order by k_reduce_splitk
@@ -271,18 +275,25 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
             const float* a = reinterpret_cast<const float*>(As + buf * KT * PA);
             const float* b = reinterpret_cast<const float*>(Bs + buf * KT * PB);
             const int boff = 4 * (l32 >> 1) + 2 * half + (l32 & 1);
+            // operands of step kk + 1 are read into the other register set
+            // while the MFMAs of step kk issue
+            float av[2][WMF], bv[2][WNF];
+            auto rd = [&](int kk, int q) {
+#pragma unroll
+                for (int i = 0; i < WMF; ++i) av[q][i] = a[2 * (kk * PA + wm + i * 32 + l32) + half];
+#pragma unroll
+                for (int j = 0; j < WNF; ++j) bv[q][j] = b[4 * (kk * PB + wn + j * 16) + boff];
+            };
+            rd(0, 0);
 #pragma unroll
             for (int kk = 0; kk < KT; ++kk) {
-                float av[WMF], bv[WNF];
-#pragma unroll
-                for (int i = 0; i < WMF; ++i) av[i] = a[2 * (kk * PA + wm + i * 32 + l32) + half];
-#pragma unroll
-                for (int j = 0; j < WNF; ++j) bv[j] = b[4 * (kk * PB + wn + j * 16) + boff];
+                if (kk + 1 < KT) rd(kk + 1, (kk + 1) & 1);
+                __builtin_amdgcn_sched_barrier(0);    // keep the reads ahead of the MFMAs
 #pragma unroll
                 for (int i = 0; i < WMF; ++i)
 #pragma unroll
                     for (int j = 0; j < WNF; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk & 1][i], bv[kk & 1][j], acc[i][j], 0, 0, 0);
             }
         } else {
             const __bf16* ah = Ah + buf * BM * RA;
@@ -353,6 +364,275 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
                 }
                 reinterpret_cast<float*>(Cb + e)[l32 & 1] = acc[i][j][r];
             }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 3M: three real products per complex product,
+//   P1 = Ar Br,  P2 = Ai Bi,  P3 = (Ar + Ai)(Br + Bi),
+//   Re C = P1 - P2,  Im C = P3 - P1 - P2,
+// each a real 32 x 32 x 2 MFMA (6 MNK executed flops against 8 MNK for 4M).
+// Operands are staged as three real planes per matrix ([plane][k][m] and
+// [plane][k][n], the sums formed on the way into LDS); a wave owns WMF x WNF
+// blocks of 32 x 32 (complex) outputs with three accumulators each.  Same
+// decomposition (slice-block fold, outer copies, split-K ranges) and the
+// same K order as k_cgemm, so a result does not depend on the tile chosen.
+template <int WGM, int WGN, int WMF, int WNF>
+struct Smem3 {
+    static constexpr int KT = KT_FP32;
+    static constexpr int BM = WGM * 32 * WMF;
+    static constexpr int BN = WGN * 32 * WNF;
+    // +32 floats per k row: lanes of the two halves of a wave read rows k
+    // and k + 1 in disjoint banks
+    static constexpr int PA = BM + 32;
+    static constexpr int PB = BN + 32;
+    static constexpr size_t bytes = 2 * 3 * (size_t)KT * (PA + PB) * 4;
+};
+
+template <int WGM, int WGN, int WMF, int WNF, bool TA, bool TB>
+__global__ void __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(2)))
+k_cgemm3m(GemmArgs g) {
+    using S = Smem3<WGM, WGN, WMF, WNF>;
+    constexpr int KT = S::KT;
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int BM = S::BM, BN = S::BN, PA = S::PA, PB = S::PB;
+    constexpr int FA = BM * KT / 2;
+    constexpr int FB = KT * BN / 2;
+    constexpr int LA = (FA + NT - 1) / NT;
+    constexpr int LB = (FB + NT - 1) / NT;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+
+    const int Mt = g.fold == 2 ? g.M * g.nr : g.M;
+    const int Nt = g.fold == 1 ? g.N * g.nr : g.N;
+    const int lgM = __builtin_ctz((unsigned)g.M), lgN = __builtin_ctz((unsigned)g.N);
+    const int tiles_m = (Mt + BM - 1) / BM;
+    const int tiles_n = (Nt + BN - 1) / BN;
+    const size_t tiles = (size_t)tiles_m * tiles_n;
+    size_t blk = blockIdx.x;
+    const size_t tile = blk % tiles;
+    blk /= tiles;
+    const int split = (int)(blk % g.splits);
+    blk /= g.splits;
+    const size_t ib = blk % g.nbatch;
+    blk /= g.nbatch;
+    const size_t bb = blk % g.nb;
+    const size_t rr = g.fold == 0 ? blk / g.nb : 0;
+    const size_t outer = g.fold == 0 ? rr * g.nb + bb : bb;
+    const size_t n_outer = g.fold == 0 ? (size_t)g.nr * g.nb : (size_t)g.nb;
+    const int tm = (int)(tile % tiles_m);
+    const int tn = (int)(tile / tiles_m);
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int kper = g.K / g.splits;
+    const int kb = split * kper, ke = kb + kper;
+    const float2* A = g.A + bb * g.sAb + ib * g.sAi + pext_u(rr, g.mA) * g.sAr;
+    const float2* B = g.B + bb * g.sBb + ib * g.sBi + pext_u(rr, g.mB) * g.sBr;
+    const long long sAf = g.fold == 2 ? g.sAr : 0;
+    const long long sBf = g.fold == 1 ? g.sBr : 0;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = (wave % WGM) * (32 * WMF);
+    const int wn = (wave / WGM) * (32 * WNF);
+    const int half = lane >> 5;
+    const int l32 = lane & 31;
+
+    floatx16 acc[WMF][WNF][3];
+#pragma unroll
+    for (int i = 0; i < WMF; ++i)
+#pragma unroll
+        for (int j = 0; j < WNF; ++j)
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][j][p][r] = 0.f;
+
+    float4 ra[LA], rb[LB];
+    auto adA = [&](int mp, int k) -> size_t {
+        const int m = mp & (g.M - 1);
+        return (size_t)(mp >> lgM) * sAf + (TA ? (size_t)k * g.M + m : (size_t)m * g.K + k);
+    };
+    auto adB = [&](int k, int np) -> size_t {
+        const int n = np & (g.N - 1);
+        return (size_t)(np >> lgN) * sBf + (TB ? (size_t)n * g.K + k : (size_t)k * g.N + n);
+    };
+    auto ldA = [&](int m, int k) -> float2 {
+        if (m0 + m >= Mt || k >= ke) return make_float2(0.f, 0.f);
+        return A[adA(m0 + m, k)];
+    };
+    auto ldB = [&](int k, int n) -> float2 {
+        if (n0 + n >= Nt || k >= ke) return make_float2(0.f, 0.f);
+        return B[adB(k, n0 + n)];
+    };
+    auto load = [&](int k0) {
+        const bool fullA = (m0 + BM <= Mt) && (k0 + KT <= ke) && (!TA || g.M >= 2);
+        const bool fullB = (n0 + BN <= Nt) && (k0 + KT <= ke) && (TB || g.N >= 2);
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            const int f = tid + i * NT;
+            if (f >= FA) break;
+            if (!TA) {
+                const int m = f / (KT / 2), k = 2 * (f % (KT / 2));
+                if (fullA) ra[i] = *reinterpret_cast<const float4*>(A + adA(m0 + m, k0 + k));
+                else {
+                    float2 x = ldA(m, k0 + k), y = ldA(m, k0 + k + 1);
+                    ra[i] = make_float4(x.x, x.y, y.x, y.y);
+                }
+            } else {
+                const int k = f / (BM / 2), m = 2 * (f % (BM / 2));
+                if (fullA) ra[i] = *reinterpret_cast<const float4*>(A + adA(m0 + m, k0 + k));
+                else {
+                    float2 x = ldA(m, k0 + k), y = ldA(m + 1, k0 + k);
+                    ra[i] = make_float4(x.x, x.y, y.x, y.y);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < LB; ++i) {
+            const int f = tid + i * NT;
+            if (f >= FB) break;
+            if (!TB) {
+                const int k = f / (BN / 2), n = 2 * (f % (BN / 2));
+                if (fullB) rb[i] = *reinterpret_cast<const float4*>(B + adB(k0 + k, n0 + n));
+                else {
+                    float2 x = ldB(k0 + k, n), y = ldB(k0 + k, n + 1);
+                    rb[i] = make_float4(x.x, x.y, y.x, y.y);
+                }
+            } else {
+                const int n = f / (KT / 2), k = 2 * (f % (KT / 2));
+                if (fullB) rb[i] = *reinterpret_cast<const float4*>(B + adB(k0 + k, n0 + n));
+                else {
+                    float2 x = ldB(k0 + k, n), y = ldB(k0 + k + 1, n);
+                    rb[i] = make_float4(x.x, x.y, y.x, y.y);
+                }
+            }
+        }
+    };
+
+    float* As = reinterpret_cast<float*>(smem);     // [2][3][KT][PA]
+    float* Bs = As + 2 * 3 * KT * PA;               // [2][3][KT][PB]
+    constexpr int QA = KT * PA, QB = KT * PB;       // plane strides
+
+    auto store = [&](int buf) {
+        float* a = As + buf * 3 * QA;
+        float* b = Bs + buf * 3 * QB;
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            const int f = tid + i * NT;
+            if (f >= FA) break;
+            const float4 v = ra[i];
+            if (TA) {
+                // (m, k), (m + 1, k): adjacent in every plane
+                const int k = f / (BM / 2), m = 2 * (f % (BM / 2));
+                *reinterpret_cast<float2*>(a + k * PA + m) = make_float2(v.x, v.z);
+                *reinterpret_cast<float2*>(a + QA + k * PA + m) = make_float2(v.y, v.w);
+                *reinterpret_cast<float2*>(a + 2 * QA + k * PA + m) = make_float2(v.x + v.y, v.z + v.w);
+            } else {
+                const int m = f / (KT / 2), k = 2 * (f % (KT / 2));
+                a[k * PA + m] = v.x;
+                a[QA + k * PA + m] = v.y;
+                a[2 * QA + k * PA + m] = v.x + v.y;
+                a[(k + 1) * PA + m] = v.z;
+                a[QA + (k + 1) * PA + m] = v.w;
+                a[2 * QA + (k + 1) * PA + m] = v.z + v.w;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < LB; ++i) {
+            const int f = tid + i * NT;
+            if (f >= FB) break;
+            const float4 v = rb[i];
+            if (!TB) {
+                const int k = f / (BN / 2), n = 2 * (f % (BN / 2));
+                *reinterpret_cast<float2*>(b + k * PB + n) = make_float2(v.x, v.z);
+                *reinterpret_cast<float2*>(b + QB + k * PB + n) = make_float2(v.y, v.w);
+                *reinterpret_cast<float2*>(b + 2 * QB + k * PB + n) = make_float2(v.x + v.y, v.z + v.w);
+            } else {
+                const int n = f / (KT / 2), k = 2 * (f % (KT / 2));
+                b[k * PB + n] = v.x;
+                b[QB + k * PB + n] = v.y;
+                b[2 * QB + k * PB + n] = v.x + v.y;
+                b[(k + 1) * PB + n] = v.z;
+                b[QB + (k + 1) * PB + n] = v.w;
+                b[2 * QB + (k + 1) * PB + n] = v.z + v.w;
+            }
+        }
+    };
+
+    auto compute = [&](int buf) {
+        const float* a = As + buf * 3 * QA;
+        const float* b = Bs + buf * 3 * QB;
+        // lane (half, l32): A[m = l32][k = half], B[k = half][n = l32];
+        // operands of step ks + 1 are read while the MFMAs of step ks issue
+        float av[2][WMF][3], bv[2][WNF][3];
+        auto rd = [&](int ks, int q) {
+            const int kr = 2 * ks + half;
+#pragma unroll
+            for (int i = 0; i < WMF; ++i)
+#pragma unroll
+                for (int p = 0; p < 3; ++p) av[q][i][p] = a[p * QA + kr * PA + wm + i * 32 + l32];
+#pragma unroll
+            for (int j = 0; j < WNF; ++j)
+#pragma unroll
+                for (int p = 0; p < 3; ++p) bv[q][j][p] = b[p * QB + kr * PB + wn + j * 32 + l32];
+        };
+        rd(0, 0);
+#pragma unroll
+        for (int ks = 0; ks < KT / 2; ++ks) {
+            if (ks + 1 < KT / 2) rd(ks + 1, (ks + 1) & 1);
+            __builtin_amdgcn_sched_barrier(0);        // keep the reads ahead of the MFMAs
+#pragma unroll
+            for (int i = 0; i < WMF; ++i)
+#pragma unroll
+                for (int j = 0; j < WNF; ++j)
+#pragma unroll
+                    for (int p = 0; p < 3; ++p)
+                        acc[i][j][p] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[ks & 1][i][p], bv[ks & 1][j][p],
+                                                                            acc[i][j][p], 0, 0, 0);
+        }
+    };
+
+    const int nk = (kper + KT - 1) / KT;
+    load(kb);
+    store(0);
+    __syncthreads();
+    for (int t = 0; t < nk; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < nk) load(kb + (t + 1) * KT);
+        compute(buf);
+        if (t + 1 < nk) store(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: acc[i][j][p][r] is row 8*(r/4) + 4*half + r%4, column l32
+    const bool part = g.splits > 1;
+    float2* Cb = part ? g.P + (((size_t)split * n_outer + outer) * g.nbatch + ib) * (size_t)Mt * Nt
+                      : g.C + bb * g.sCb + ib * g.sCi + rr * g.sCr;
+    const long long sCm = g.fold == 2 ? g.sCr : 0, sCn = g.fold == 1 ? g.sCr : 0;
+#pragma unroll
+    for (int i = 0; i < WMF; ++i)
+#pragma unroll
+        for (int j = 0; j < WNF; ++j) {
+            const int np = n0 + wn + j * 32 + l32;
+            if (np >= Nt) continue;
+            const int n = np & (g.N - 1);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int mp = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (mp >= Mt) continue;
+                size_t e;
+                if (part) e = (size_t)mp * Nt + np;
+                else {
+                    const int m = mp & (g.M - 1);
+                    e = (size_t)(mp >> lgM) * sCm + (size_t)(np >> lgN) * sCn +
+                        (g.transC ? (size_t)n * g.M + m : (size_t)m * g.N + n);
+                }
+                const float p1 = acc[i][j][0][r], p2 = acc[i][j][1][r], p3 = acc[i][j][2][r];
+                Cb[e] = make_float2(p1 - p2, p3 - p1 - p2);
+            }
+            // one block at a time: keeps the accumulators from being copied
+            // out all at once (register pressure sets the occupancy)
+            __builtin_amdgcn_sched_barrier(0);
         }
 }
 
@@ -515,6 +795,30 @@ static void launch_cfg(const GemmArgs& g, size_t grid, hipStream_t s) {
     }
 }
 
+template <int WGM, int WGN, int WMF, int WNF, bool TA, bool TB>
+static void launch_one3(const GemmArgs& g, size_t grid, hipStream_t s) {
+    const size_t lds = Smem3<WGM, WGN, WMF, WNF>::bytes;
+    auto* fn = &k_cgemm3m<WGM, WGN, WMF, WNF, TA, TB>;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr = true;
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64 * WGM * WGN), lds, s, g);
+}
+
+template <int WGM, int WGN, int WMF, int WNF>
+static void launch_cfg3(const GemmArgs& g, size_t grid, hipStream_t s) {
+    if (g.transA) {
+        if (g.transB) launch_one3<WGM, WGN, WMF, WNF, true, true>(g, grid, s);
+        else launch_one3<WGM, WGN, WMF, WNF, true, false>(g, grid, s);
+    } else {
+        if (g.transB) launch_one3<WGM, WGN, WMF, WNF, false, true>(g, grid, s);
+        else launch_one3<WGM, WGN, WMF, WNF, false, false>(g, grid, s);
+    }
+}
+
 template <int WGM, int WGN, int WMF, int WNF>
 static void launch_prec(const GemmArgs& g, int precision, size_t grid, hipStream_t s) {
     if (precision == 2) launch_cfg<2, WGM, WGN, WMF, WNF>(g, grid, s);
@@ -561,9 +865,14 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
     } else {
         int bm = 128, bn = 128;
         if (c.kind == GEMM_MFMA_64x64) { bm = 64; bn = 64; }
-        if (c.kind == GEMM_MFMA_128x16) { bm = 128; bn = 16; }
+        if (c.kind == GEMM_MFMA_128x16) { bm = 128; bn = precision == 1 ? 32 : 16; }
         const size_t grid = (size_t)((Mt + bm - 1) / bm) * ((Nt + bn - 1) / bn) * batches;
-        if (c.kind == GEMM_MFMA_128x128) launch_prec<2, 2, 2, 4>(g, precision, grid, s);
+        if (precision == 1) {
+            // 3M tiles: 128 x 128, 64 x 64, and 128 x 32 for the skinny shapes
+            if (c.kind == GEMM_MFMA_128x128) launch_cfg3<2, 2, 2, 2>(g, grid, s);
+            else if (c.kind == GEMM_MFMA_64x64) launch_cfg3<2, 2, 1, 1>(g, grid, s);
+            else launch_cfg3<4, 1, 1, 1>(g, grid, s);
+        } else if (c.kind == GEMM_MFMA_128x128) launch_prec<2, 2, 2, 4>(g, precision, grid, s);
         else if (c.kind == GEMM_MFMA_64x64) launch_prec<2, 2, 1, 2>(g, precision, grid, s);
         else launch_prec<4, 1, 1, 1>(g, precision, grid, s);
     }
