@@ -102,7 +102,9 @@ def cpu_baseline(circ, word, seconds=20.0, width=24, seed=0):
 def serve_bench(args):
     """The served mixed stream: requests drawn uniformly from four circuit
     families (three instances each, all plans resident), 1..64 bitstrings
-    each, Poisson arrivals at 0.7 x the measured saturation throughput."""
+    each, Poisson arrivals at a fixed fraction of the saturation rate.  The
+    saturation rate is 1 / E[service time], with each family's time per
+    bitstring measured alone first."""
     import numpy as np
     import torch
     from circuits import random_bitstrings
@@ -113,13 +115,28 @@ def serve_bench(args):
     prec = B.PRECISIONS[args.precision]
     t = time.perf_counter()
     plans = [make_plan(c, n_slices=ns, B=32) for _, c, ns in pool]
-    log("12 plans built in %.1f s" % (time.perf_counter() - t))
+    log("%d plans built in %.1f s" % (len(plans), time.perf_counter() - t))
     free, _ = torch.cuda.mem_get_info(0)
     eng = B.Engine(0, arena_bytes=int(free - (8 << 30)))
     B.tn_server_config(eng.ctx, args.slots, 64)
     hs = [eng.load(p.to_blob()) for p in plans]
-    rng = np.random.Generator(np.random.PCG64(5002))
     fams = sorted(set(f for f, _, _ in pool))
+    # time per bitstring of each family, alone (first instance, 8 bitstrings)
+    per_b = {}
+    for f in fams:
+        k = [i for i, (ff, _, _) in enumerate(pool) if ff == f][0]
+        w = random_bitstrings(pool[k][1].n, 8, 89000 + k)
+        eng.amplitudes(hs[k], w[:1], prec)
+        t0 = time.perf_counter()
+        eng.amplitudes(hs[k], w, prec)
+        per_b[f] = (time.perf_counter() - t0) / len(w)
+        log("family %s: %.4f s per bitstring alone" % (f, per_b[f]))
+    mean_nb = 32.5
+    e_service = sum(per_b[f] * mean_nb for f in fams) / len(fams)
+    sat = 1.0 / e_service
+    lam = args.serve_load * sat
+    log("E[service] %.2f s -> saturation %.4f req/s, arrivals at %.4f req/s" % (e_service, sat, lam))
+    rng = np.random.Generator(np.random.PCG64(5002))
 
     def draw(i):
         f = fams[int(rng.integers(len(fams)))]
@@ -128,39 +145,30 @@ def serve_bench(args):
         nb = int(rng.integers(1, 65))
         return k, random_bitstrings(pool[k][1].n, nb, 90000 + i)
 
-    def run(reqs, arrivals):
-        t0 = time.perf_counter()
-        pending = {}
-        done = {}
-        i = 0
-        while i < len(reqs) or pending:
-            now = time.perf_counter() - t0
-            while i < len(reqs) and arrivals[i] <= now:
-                k, w = reqs[i]
-                pending[B.tn_submit(eng.ctx, hs[k], w, prec)] = (i, len(w))
-                i += 1
-            for tk in list(pending):
-                j, n = pending[tk]
-                r = B.tn_poll(eng.ctx, tk, n)
-                if r is not None:
-                    done[j] = r
-                    del pending[tk]
-                    log("request %d (%s, %d bitstrings) done after %.2f s" % (
-                        j, pool[reqs[j][0]][0], n,
-                        (r[1]["t_end_ns"] - r[1]["t_arrive_ns"]) * 1e-9))
-            time.sleep(0.0005)
-        return done, time.perf_counter() - t0
-
-    # saturation: a burst of requests submitted at once
-    burst = [draw(i) for i in range(args.serve_burst)]
-    done, el = run(burst, [0.0] * len(burst))
-    sat = len(burst) / el
-    log("saturation: %d requests in %.1f s -> %.3f req/s" % (len(burst), el, sat))
-    lam = 0.7 * sat
     reqs = [draw(1000 + i) for i in range(args.serve_requests)]
     gaps = rng.exponential(1.0 / lam, size=len(reqs))
     arrivals = np.cumsum(gaps) - gaps[0]
-    done, el = run(reqs, arrivals)
+    t0 = time.perf_counter()
+    pending = {}
+    done = {}
+    i = 0
+    while i < len(reqs) or pending:
+        now = time.perf_counter() - t0
+        while i < len(reqs) and arrivals[i] <= now:
+            k, w = reqs[i]
+            pending[B.tn_submit(eng.ctx, hs[k], w, prec)] = (i, len(w))
+            log("request %d (%s, %d bitstrings) submitted at %.1f s" % (i, pool[k][0], len(w), now))
+            i += 1
+        for tk in list(pending):
+            j, n = pending[tk]
+            r = B.tn_poll(eng.ctx, tk, n)
+            if r is not None:
+                done[j] = r
+                del pending[tk]
+                log("request %d (%s, %d bitstrings) done after %.2f s" % (
+                    j, pool[reqs[j][0]][0], n, (r[1]["t_end_ns"] - r[1]["t_arrive_ns"]) * 1e-9))
+        time.sleep(0.0005)
+    el = time.perf_counter() - t0
     lat = np.array([(done[j][1]["t_end_ns"] - done[j][1]["t_arrive_ns"]) * 1e-9 for j in range(len(reqs))])
     amps = sum(len(w) for _, w in reqs)
     # the same request alone gives the same numbers
@@ -174,9 +182,12 @@ def serve_bench(args):
     out = {"metric": "p50/p99 served latency, mixed stream", "unit": "s",
            "p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
            "req_per_s": len(reqs) / el, "amplitudes_per_s": amps / el,
-           "lambda_req_per_s": lam, "saturation_req_per_s": sat, "n_requests": len(reqs),
-           "slots": args.slots, "alone_equals_mixed": same, "precision": args.precision,
+           "lambda_req_per_s": lam, "saturation_req_per_s": sat, "load": args.serve_load,
+           "n_requests": len(reqs), "slots": args.slots, "alone_equals_mixed": same,
+           "precision": args.precision,
+           "seconds_per_bitstring_alone": per_b,
            "p50_by_family": {f: float(np.percentile(v, 50)) for f, v in per_fam.items()},
+           "p99_by_family": {f: float(np.percentile(v, 99)) for f, v in per_fam.items()},
            "config": {"workload": "served mix: 5x5 d10, 6x6 d12, 8x8 d16 (2^10 slices) "
                                   "Haar SU(2)+CZ lattices and 3x3x4 SU(4) stack, "
                                   "1-64 bitstrings per request, Poisson arrivals"},
@@ -200,8 +211,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--serve", action="store_true", help="served mixed stream instead")
-    ap.add_argument("--serve-requests", type=int, default=60)
-    ap.add_argument("--serve-burst", type=int, default=16)
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="arrival rate as a fraction of the saturation rate")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a 1 GiB device copy, to scale the HBM byte counters")

@@ -145,6 +145,14 @@ int tn_cancel(tn_ctx* ctx, uint64_t ticket);
  * batch.  Call before the first tn_submit. */
 int tn_server_config(tn_ctx* ctx, int32_t n_slots, int32_t max_batch);
 
+/* Heavy batches: a merged batch whose algorithmic work (the plan's flops
+ * per bitstring, summed over slices, times its bitstrings) is at least
+ * `heavy_flops` runs only while fewer than `max_heavy` other heavy batches
+ * run; lighter batches use the remaining slots meanwhile.  Defaults 1e14 and
+ * 1.  May be called at any time; TN_EINVAL for a negative threshold or
+ * max_heavy < 1. */
+int tn_server_set_heavy(tn_ctx* ctx, double heavy_flops, int32_t max_heavy);
+
 /* Stop the scheduler and slot threads (pending work finishes first);
  * tn_ctx_destroy calls it. */
 int tn_server_stop(tn_ctx* ctx);

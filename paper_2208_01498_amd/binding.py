@@ -21,7 +21,7 @@ PRECISIONS = {"fp32": TN_FP32_4M, "fp32_3m": TN_FP32_3M, "bf16x3": TN_SPLIT_BF16
 
 EXPORTED = ["tn_ctx_create", "tn_ctx_destroy", "tn_plan_load", "tn_plan_validate",
             "tn_plan_info", "tn_plan_unload", "tn_contract_amplitudes", "tn_submit",
-            "tn_poll", "tn_cancel", "tn_server_config", "tn_server_stop",
+            "tn_poll", "tn_cancel", "tn_server_config", "tn_server_set_heavy", "tn_server_stop",
             "tn_last_exec_stats", "tn_ctx_set_profiling", "tn_ctx_set_slice_block", "tn_kernel_cgemm", "tn_kernel_cgemm_scratch_bytes", "tn_kernel_permute",
             "tn_last_error"]
 
@@ -86,6 +86,7 @@ def load_library(path=LIB_PATH):
         "tn_poll": [vp, ctypes.c_uint64, dp, ctypes.POINTER(tn_req_stats)],
         "tn_cancel": [vp, ctypes.c_uint64],
         "tn_server_config": [vp, i32, i32],
+        "tn_server_set_heavy": [vp, ctypes.c_double, i32],
         "tn_server_stop": [vp],
         "tn_last_exec_stats": [vp, ctypes.POINTER(tn_exec_stats)],
         "tn_ctx_set_profiling": [vp, i32],
@@ -188,6 +189,10 @@ def tn_cancel(ctx, ticket):
 
 def tn_server_config(ctx, n_slots, max_batch):
     _check(load_library().tn_server_config(ctx, n_slots, max_batch))
+
+
+def tn_server_set_heavy(ctx, heavy_flops, max_heavy):
+    _check(load_library().tn_server_set_heavy(ctx, float(heavy_flops), max_heavy))
 
 
 def tn_server_stop(ctx):

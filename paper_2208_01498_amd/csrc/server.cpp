@@ -5,7 +5,10 @@
 // max_batch bitstrings), admits the batch when an execution slot is idle and
 // the arena can hold the plan's workspace for it (the workspace of a chunk
 // of one bitstring at least; larger chunks when memory allows), and hands it
-// to the slot.  Each slot owns a HIP stream and a worker thread, so admitted
+// to the slot.  A batch whose algorithmic work reaches the heavy threshold
+// counts against a limit of concurrently running heavy batches, so light
+// requests keep finding a slot beside long contractions; a batch that
+// cannot start does not block the ones queued behind it.  Each slot owns a HIP stream and a worker thread, so admitted
 // batches run concurrently on the device while new requests keep arriving.
 // A result does not depend on what it was batched or overlapped with: the
 // per-bitstring arithmetic is the same for any chunk size.
@@ -105,75 +108,84 @@ static void scheduler(tn_ctx* ctx) {
             return false;
         });
         if (ctx->stop) return;
-        // drop cancelled heads
-        while (!ctx->queue.empty() && ctx->queue.front()->cancelled) {
-            auto r = ctx->queue.front();
-            ctx->queue.pop_front();
-            r->status = TN_ECANCELLED;
-            const_cast<tn_plan*>(r->plan)->pending--;
-        }
-        if (ctx->queue.empty()) continue;
         Slot* slot = nullptr;
-        for (auto& s : ctx->slots)
-            if (!s->busy) { slot = s.get(); break; }
-        if (!slot) continue;
-        auto head = ctx->queue.front();
-        tn_plan* plan = const_cast<tn_plan*>(head->plan);
-        // merge queued requests on the same plan and precision
-        std::vector<std::shared_ptr<Request>> job;
-        int total = 0;
-        for (auto it = ctx->queue.begin(); it != ctx->queue.end();) {
-            auto& r = *it;
-            if (r->plan == head->plan && r->precision == head->precision && !r->cancelled &&
-                (job.empty() || total + (int)r->bits.size() <= ctx->max_batch)) {
-                total += (int)r->bits.size();
-                job.push_back(r);
-                it = ctx->queue.erase(it);
-            } else {
-                ++it;
-            }
+        bool any_busy = false;
+        int heavy_busy = 0;
+        for (auto& s : ctx->slots) {
+            if (!s->busy && !slot) slot = s.get();
+            any_busy |= s->busy;
+            heavy_busy += s->busy && s->heavy;
         }
-        // admission: the largest chunk (<= total) whose workspace fits a free region
-        size_t avail = largest_free(ctx);
-        size_t need1 = plan->mem(1, 0).bytes;
-        if (need1 > avail) {
-            // not admissible now: put the job back in arrival order and wait
-            for (auto it = job.rbegin(); it != job.rend(); ++it) ctx->queue.push_front(*it);
-            bool any_busy = false;
-            for (auto& s : ctx->slots) any_busy |= s->busy;
-            if (!any_busy) {
-                // can never fit (arena smaller than one bitstring's workspace)
-                auto r = ctx->queue.front();
-                ctx->queue.pop_front();
-                r->status = TN_ENOMEM;
-                plan->pending--;
+        if (!slot) continue;
+        // first admissible batch in arrival order: a queued request plus the
+        // later ones on the same plan and precision (up to max_batch); a
+        // batch that cannot start now (memory, or the heavy-batch limit)
+        // does not hold back the requests behind it
+        bool admitted = false;
+        for (auto hit = ctx->queue.begin(); hit != ctx->queue.end(); ++hit) {
+            auto head = *hit;
+            tn_plan* plan = const_cast<tn_plan*>(head->plan);
+            int total = 0;
+            for (auto it = hit; it != ctx->queue.end(); ++it) {
+                auto& r = *it;
+                if (r->plan == head->plan && r->precision == head->precision && !r->cancelled &&
+                    (total == 0 || total + (int)r->bits.size() <= ctx->max_batch))
+                    total += (int)r->bits.size();
+            }
+            const bool heavy = plan->host.flops_total_per_b * total >= ctx->heavy_flops;
+            if (heavy && heavy_busy >= ctx->max_heavy) continue;
+            const size_t avail = largest_free(ctx);
+            const size_t need1 = plan->mem(1, 0).bytes;
+            if (need1 > avail) {
+                if (!any_busy) {
+                    // the whole arena is free and still too small
+                    ctx->queue.erase(hit);
+                    head->status = TN_ENOMEM;
+                    plan->pending--;
+                    admitted = true;     // the queue changed: scan again
+                    break;
+                }
                 continue;
             }
-            ctx->scv.wait(lk);
-            continue;
+            std::vector<std::shared_ptr<Request>> job;
+            int taken = 0;
+            for (auto it = hit; it != ctx->queue.end();) {
+                auto& r = *it;
+                if (r->plan == head->plan && r->precision == head->precision && !r->cancelled &&
+                    (job.empty() || taken + (int)r->bits.size() <= ctx->max_batch)) {
+                    taken += (int)r->bits.size();
+                    job.push_back(r);
+                    it = ctx->queue.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+            // execution shape for the free region, one batch taking at most
+            // half of the arena when it can run in less; reserve exactly
+            // that shape's workspace
+            int r = 0, ch = 0;
+            const size_t cap = std::max(need1, std::min(avail, ctx->arena_bytes / 2));
+            choose_shape(plan, taken, cap, ctx->force_slice_block, r, ch);
+            const size_t bytes = plan->mem(ch, r).bytes;
+            size_t off = 0;
+            arena_alloc(ctx, bytes, &off);
+            const int64_t t = now_ns();
+            for (auto& q : job) q->st.t_admit_ns = t;
+            slot->busy = true;
+            slot->heavy = heavy;
+            slot->job = job;
+            slot->plan = plan;
+            slot->precision = head->precision;
+            slot->off = off;
+            slot->bytes = bytes;
+            slot->shape_r = r;
+            slot->shape_chunk = ch;
+            slot->has_job = true;
+            slot->cv.notify_all();
+            admitted = true;
+            break;
         }
-        // execution shape for the largest free region; reserve exactly its
-        // workspace (the batch then runs in that shape)
-        // one batch takes at most half of the arena when it can run in less,
-        // so that other requests keep being admitted beside it
-        int r = 0, ch = 0;
-        size_t cap = std::max(need1, std::min(avail, ctx->arena_bytes / 2));
-        choose_shape(plan, total, cap, ctx->force_slice_block, r, ch);
-        size_t bytes = plan->mem(ch, r).bytes;
-        size_t off = 0;
-        arena_alloc(ctx, bytes, &off);
-        int64_t t = now_ns();
-        for (auto& r : job) r->st.t_admit_ns = t;
-        slot->busy = true;
-        slot->job = job;
-        slot->plan = plan;
-        slot->precision = head->precision;
-        slot->off = off;
-        slot->bytes = bytes;
-        slot->shape_r = r;
-        slot->shape_chunk = ch;
-        slot->has_job = true;
-        slot->cv.notify_all();
+        if (!admitted) ctx->scv.wait(lk);
     }
 }
 
@@ -206,6 +218,15 @@ int tn_server_config(tn_ctx* ctx, int32_t n_slots, int32_t max_batch) {
     if (ctx->sched_started) { set_error("server already running"); return TN_EBUSY; }
     ctx->n_slots = n_slots;
     ctx->max_batch = max_batch;
+    return TN_OK;
+}
+
+int tn_server_set_heavy(tn_ctx* ctx, double heavy_flops, int32_t max_heavy) {
+    if (!ctx || !(heavy_flops >= 0) || max_heavy < 1) { set_error("bad heavy-batch limit"); return TN_EINVAL; }
+    std::lock_guard<std::mutex> g(ctx->smu);
+    ctx->heavy_flops = heavy_flops;
+    ctx->max_heavy = max_heavy;
+    ctx->scv.notify_all();
     return TN_OK;
 }
 

@@ -147,6 +147,7 @@ struct Slot {
     int precision = 0;
     size_t off = 0, bytes = 0;
     int shape_r = 0, shape_chunk = 0;
+    bool heavy = false;
     std::condition_variable cv;
 };
 
@@ -173,6 +174,8 @@ struct tn_ctx {
     bool stop = false;
     int n_slots = 4;
     int max_batch = 64;
+    double heavy_flops = 1e14;           // algorithmic flops of a heavy batch
+    int max_heavy = 1;                   // heavy batches running at once
     std::vector<std::unique_ptr<tn::Slot>> slots;
     // arena sub-allocation for served batches: (offset, size) free list
     std::map<size_t, size_t> free_list;

@@ -121,3 +121,39 @@ def test_submit_rejects_requests_that_never_fit():
         assert e.value.code == B.TN_ENOMEM
     finally:
         eng.close()
+
+
+def test_light_request_passes_a_waiting_heavy_batch():
+    """With one heavy batch allowed at a time, a second heavy request waits
+    for the first while a light request submitted after it is admitted at
+    once; every result equals its alone run."""
+    from paper_2208_01498_amd import binding as B
+    from paper_2208_01498_amd.planner.plan import make_plan
+    heavy_c = lattice_circuit(6, 6, 12, 620, "haar", "cz")
+    light_c = lattice_circuit(3, 3, 6, 621, "haar", "cz")
+    hp, lp = make_plan(heavy_c, B=16), make_plan(light_c, B=2)
+    eng = B.Engine(0, arena_bytes=2 << 30)
+    try:
+        B.tn_server_config(eng.ctx, 3, 16)
+        hh, hl = eng.load(hp.to_blob()), eng.load(lp.to_blob())
+        info = B.tn_plan_info(hh)
+        B.tn_server_set_heavy(eng.ctx, info["flops_total_per_b"] * 16, 1)
+        w1 = random_bitstrings(36, 16, 622)
+        w2 = random_bitstrings(36, 16, 623)
+        wl = random_bitstrings(9, 2, 624)
+        alone = [eng.amplitudes(hh, w1, 0), eng.amplitudes(hh, w2, 0), eng.amplitudes(hl, wl, 0)]
+        print("submitting heavy, heavy, light", flush=True)
+        ts = [B.tn_submit(eng.ctx, hh, w1, 0), B.tn_submit(eng.ctx, hh, w2, 0),
+              B.tn_submit(eng.ctx, hl, wl, 0)]
+        res = _wait(B, eng.ctx, ts, [16, 16, 2])
+        (a1, s1), (a2, s2), (al, sl) = res[ts[0]], res[ts[1]], res[ts[2]]
+        print("heavy 1 %.3f-%.3f s, heavy 2 admitted %.3f s, light %.3f-%.3f s" % (
+            (s1["t_start_ns"] - s1["t_arrive_ns"]) * 1e-9, (s1["t_end_ns"] - s1["t_arrive_ns"]) * 1e-9,
+            (s2["t_admit_ns"] - s1["t_arrive_ns"]) * 1e-9, (sl["t_start_ns"] - s1["t_arrive_ns"]) * 1e-9,
+            (sl["t_end_ns"] - s1["t_arrive_ns"]) * 1e-9), flush=True)
+        assert s2["t_admit_ns"] >= s1["t_end_ns"]
+        assert sl["t_admit_ns"] <= s2["t_admit_ns"]
+        for got, want in zip((a1, a2, al), alone):
+            assert np.array_equal(got, want)
+    finally:
+        eng.close()
