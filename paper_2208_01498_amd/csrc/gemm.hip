@@ -20,10 +20,11 @@
 //   split-K         when a shape has too few output tiles to fill the chip,
 //                   K is cut into a fixed number of ranges whose partial
 //                   products are summed in range order by k_reduce_splitk
-// Tiles: 4 waves per workgroup; a wave owns WMF x WNF blocks of 32 x 16
-// (complex); KT = 16 complex k per stage; global loads of the next stage are
-// issued before the MFMAs of the current one and land in the other half of
-// a double-buffered LDS, one barrier per stage.
+// Tiles: WGM x WGN waves per workgroup (4 or 8); a wave owns WMF x WNF
+// blocks of 32 x 16 (4M, split) or 32 x 32 (3M) complex outputs; 8 (FP32) or
+// 16 (split) complex k per stage; global loads of the next stage are issued
+// before the MFMAs of the current one and land in the other half of a
+// double-buffered LDS, one barrier per stage.
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 #include <stdint.h>
@@ -86,10 +87,10 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
     constexpr int LB = (FB + NT - 1) / NT;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
-    // slice-block folding: Mt = M * nr (fold 2) or Nt = N * nr (fold 1); the
-    // folded index m' = r * M + m selects operand and output block r
-    const int Mt = g.fold == 2 ? g.M * g.nr : g.M;
-    const int Nt = g.fold == 1 ? g.N * g.nr : g.N;
+    // slice-block folding: the folded index m' = a * M + m selects operand
+    // and output copy a (likewise n')
+    const int Mt = gemm_rows(g);
+    const int Nt = gemm_cols(g);
     const int lgM = __builtin_ctz((unsigned)g.M), lgN = __builtin_ctz((unsigned)g.N);
     const int tiles_m = (Mt + BM - 1) / BM;
     const int tiles_n = (Nt + BN - 1) / BN;
@@ -112,8 +113,8 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
     const int kb = split * kper, ke = kb + kper;
     const float2* A = g.A + bb * g.sAb + ib * g.sAi + pext_u(rr, g.mA) * g.sAr;
     const float2* B = g.B + bb * g.sBb + ib * g.sBi + pext_u(rr, g.mB) * g.sBr;
-    const long long sAf = g.fold == 2 ? g.sAr : 0;    // per folded block
-    const long long sBf = g.fold == 1 ? g.sBr : 0;
+    const long long sAf = (g.fold == 2 || g.fold == 3) ? g.sAr : 0;    // per folded block
+    const long long sBf = (g.fold == 1 || g.fold == 3) ? g.sBr : 0;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -343,7 +344,6 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
     const bool part = g.splits > 1;
     float2* Cb = part ? g.P + (((size_t)split * n_outer + outer) * g.nbatch + ib) * (size_t)Mt * Nt
                       : g.C + bb * g.sCb + ib * g.sCi + rr * g.sCr;
-    const long long sCm = g.fold == 2 ? g.sCr : 0, sCn = g.fold == 1 ? g.sCr : 0;
 #pragma unroll
     for (int i = 0; i < WMF; ++i)
 #pragma unroll
@@ -359,7 +359,7 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
                 if (part) e = (size_t)mp * Nt + np;
                 else {
                     const int m = mp & (g.M - 1);
-                    e = (size_t)(mp >> lgM) * sCm + (size_t)(np >> lgN) * sCn +
+                    e = (size_t)gemm_c_copy(g, (unsigned)(mp >> lgM), (unsigned)(np >> lgN)) +
                         (g.transC ? (size_t)n * g.M + m : (size_t)m * g.N + n);
                 }
                 reinterpret_cast<float*>(Cb + e)[l32 & 1] = acc[i][j][r];
@@ -402,8 +402,8 @@ k_cgemm3m(GemmArgs g) {
     constexpr int LB = (FB + NT - 1) / NT;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
-    const int Mt = g.fold == 2 ? g.M * g.nr : g.M;
-    const int Nt = g.fold == 1 ? g.N * g.nr : g.N;
+    const int Mt = gemm_rows(g);
+    const int Nt = gemm_cols(g);
     const int lgM = __builtin_ctz((unsigned)g.M), lgN = __builtin_ctz((unsigned)g.N);
     const int tiles_m = (Mt + BM - 1) / BM;
     const int tiles_n = (Nt + BN - 1) / BN;
@@ -426,8 +426,8 @@ k_cgemm3m(GemmArgs g) {
     const int kb = split * kper, ke = kb + kper;
     const float2* A = g.A + bb * g.sAb + ib * g.sAi + pext_u(rr, g.mA) * g.sAr;
     const float2* B = g.B + bb * g.sBb + ib * g.sBi + pext_u(rr, g.mB) * g.sBr;
-    const long long sAf = g.fold == 2 ? g.sAr : 0;
-    const long long sBf = g.fold == 1 ? g.sBr : 0;
+    const long long sAf = (g.fold == 2 || g.fold == 3) ? g.sAr : 0;
+    const long long sBf = (g.fold == 1 || g.fold == 3) ? g.sBr : 0;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -608,7 +608,6 @@ k_cgemm3m(GemmArgs g) {
     const bool part = g.splits > 1;
     float2* Cb = part ? g.P + (((size_t)split * n_outer + outer) * g.nbatch + ib) * (size_t)Mt * Nt
                       : g.C + bb * g.sCb + ib * g.sCi + rr * g.sCr;
-    const long long sCm = g.fold == 2 ? g.sCr : 0, sCn = g.fold == 1 ? g.sCr : 0;
 #pragma unroll
     for (int i = 0; i < WMF; ++i)
 #pragma unroll
@@ -624,7 +623,7 @@ k_cgemm3m(GemmArgs g) {
                 if (part) e = (size_t)mp * Nt + np;
                 else {
                     const int m = mp & (g.M - 1);
-                    e = (size_t)(mp >> lgM) * sCm + (size_t)(np >> lgN) * sCn +
+                    e = (size_t)gemm_c_copy(g, (unsigned)(mp >> lgM), (unsigned)(np >> lgN)) +
                         (g.transC ? (size_t)n * g.M + m : (size_t)m * g.N + n);
                 }
                 const float p1 = acc[i][j][0][r], p2 = acc[i][j][1][r], p3 = acc[i][j][2][r];
@@ -694,13 +693,12 @@ __global__ void __launch_bounds__(256) k_cgemm_dot(GemmArgs g) {
 // Sum of split-K partials in range order, written in C's layout.  Partial
 // layout: [split][outer][inner batch][m'][n'] over the folded sizes.
 __global__ void k_reduce_splitk(GemmArgs g) {
-    const int Mt = g.fold == 2 ? g.M * g.nr : g.M;
-    const int Nt = g.fold == 1 ? g.N * g.nr : g.N;
+    const int Mt = gemm_rows(g);
+    const int Nt = gemm_cols(g);
     const int lgM = __builtin_ctz((unsigned)g.M), lgN = __builtin_ctz((unsigned)g.N);
     const size_t n_outer = g.fold == 0 ? (size_t)g.nr * g.nb : (size_t)g.nb;
     const size_t MN = (size_t)Mt * Nt;
     const size_t per = MN * g.nbatch * n_outer;
-    const long long sCm = g.fold == 2 ? g.sCr : 0, sCn = g.fold == 1 ? g.sCr : 0;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < per;
          e += (size_t)gridDim.x * blockDim.x) {
         float2 s = g.P[e];
@@ -715,8 +713,8 @@ __global__ void k_reduce_splitk(GemmArgs g) {
         const size_t bb = outer % g.nb, rr = g.fold == 0 ? outer / g.nb : 0;
         const int mp = (int)(mn / Nt), np = (int)(mn % Nt);
         const int m = mp & (g.M - 1), n = np & (g.N - 1);
-        const size_t c = bb * g.sCb + ib * g.sCi + rr * g.sCr + (size_t)(mp >> lgM) * sCm +
-                         (size_t)(np >> lgN) * sCn +
+        const size_t c = bb * g.sCb + ib * g.sCi + rr * g.sCr +
+                         (size_t)gemm_c_copy(g, (unsigned)(mp >> lgM), (unsigned)(np >> lgN)) +
                          (g.transC ? (size_t)n * g.M + m : (size_t)m * g.N + n);
         g.C[c] = s;
     }
@@ -829,13 +827,15 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
     GemmArgs g = g0;
     if (g.nr < 1) g.nr = 1;
     if (g.nr == 1) g.fold = 0;
-    const int Mt0 = g.fold == 2 ? g.M * g.nr : g.M;
-    const int Nt0 = g.fold == 1 ? g.N * g.nr : g.N;
+    const int Mt0 = gemm_rows(g);
+    const int Nt0 = gemm_cols(g);
     GemmChoice c = choose_gemm(g.M, g.N, g.K, g.nbatch, Mt0, Nt0);
     if (c.kind == GEMM_DOT && g.fold != 0) {
-        // copies as an outer batch: the folded operand takes every copy
+        // copies as an outer batch: with fold 1 or 2 the folded operand takes
+        // every copy; fold 3 keeps its masks
         const unsigned all = (unsigned)g.nr - 1;
-        if (g.fold == 1) { g.mA = 0; g.mB = all; } else { g.mA = all; g.mB = 0; }
+        if (g.fold == 1) { g.mA = 0; g.mB = all; }
+        else if (g.fold == 2) { g.mA = all; g.mB = 0; }
         g.fold = 0;
     }
     if (c.swap) {
@@ -846,12 +846,12 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
         g.sAb = g0.sBb; g.sAi = g0.sBi; g.sAr = g0.sBr; g.mA = g0.mB;
         g.sBb = g0.sAb; g.sBi = g0.sAi; g.sBr = g0.sAr; g.mB = g0.mA;
         g.transC = !g0.transC;
-        g.fold = g.fold == 1 ? 2 : g.fold == 2 ? 1 : 0;
+        g.fold = g.fold == 1 ? 2 : g.fold == 2 ? 1 : g.fold;
     }
     g.splits = c.splits;
     if (c.splits > 1 && !g.P) return hipErrorInvalidValue;
-    const int Mt = g.fold == 2 ? g.M * g.nr : g.M;
-    const int Nt = g.fold == 1 ? g.N * g.nr : g.N;
+    const int Mt = gemm_rows(g);
+    const int Nt = gemm_cols(g);
     const size_t n_outer = g.fold == 0 ? (size_t)g.nr * g.nb : (size_t)g.nb;
     const size_t batches = (size_t)g.nbatch * n_outer * c.splits;
     if (c.kind == GEMM_DOT) {
@@ -887,8 +887,9 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
 
 int gemm_kind(const GemmArgs& g, int precision) {
     (void)precision;
-    const int nr = g.nr < 1 ? 1 : g.nr;
-    const int Mt = (g.fold == 2 && nr > 1) ? g.M * nr : g.M;
-    const int Nt = (g.fold == 1 && nr > 1) ? g.N * nr : g.N;
+    GemmArgs f = g;
+    if (f.nr <= 1) { f.nr = 1; f.fold = 0; }
+    const int Mt = gemm_rows(f);
+    const int Nt = gemm_cols(f);
     return choose_gemm(g.M, g.N, g.K, g.nbatch, Mt, Nt).kind;
 }

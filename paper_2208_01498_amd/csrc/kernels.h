@@ -50,12 +50,36 @@ struct GemmArgs {
     int nb;                   // outer batch count (bitstrings)
     int nr;                   // copies of C over the slice block, 1 if none
     int fold;                 // 0: copies as an outer batch; 1: folded into N
-                              // (only B and C vary with it); 2: folded into M
-    unsigned mA, mB;          // fold 0: A's copy = pext(c, mA), B's copy = pext(c, mB)
+                              // (only B and C vary with it); 2: folded into M;
+                              // 3: A's copies into M and B's into N (disjoint
+                              // copy bits covering C's)
+    unsigned mA, mB;          // A's copy = pext(c, mA), B's copy = pext(c, mB)
+                              // for C's copy c
     long long sAb, sBb, sCb;  // outer strides (elements); 0 = broadcast
     long long sAi, sBi, sCi;  // inner strides
     long long sAr, sBr, sCr;  // slice-block strides; 0 = broadcast
 };
+
+// Folded GEMM sizes: the row index m' = a * M + m and column index
+// n' = b * N + n carry operand copies a, b when they are folded.
+__host__ __device__ inline int gemm_rows(const GemmArgs& g) {
+    return g.fold == 2 ? g.M * g.nr : g.fold == 3 ? g.M << __builtin_popcount(g.mA) : g.M;
+}
+__host__ __device__ inline int gemm_cols(const GemmArgs& g) {
+    return g.fold == 1 ? g.N * g.nr : g.fold == 3 ? g.N << __builtin_popcount(g.mB) : g.N;
+}
+// scatter the low bits of x to the set positions of m (parallel bit deposit)
+__host__ __device__ inline unsigned pdep_bits(unsigned x, unsigned m) {
+    unsigned r = 0;
+    for (; m; m &= m - 1, x >>= 1)
+        if (x & 1) r |= m & (~m + 1);
+    return r;
+}
+// element offset of C's copy for folded row block a and column block b
+__host__ __device__ inline long long gemm_c_copy(const GemmArgs& g, unsigned a, unsigned b) {
+    if (g.fold == 3) return (long long)(pdep_bits(a, g.mA) | pdep_bits(b, g.mB)) * g.sCr;
+    return (long long)a * (g.fold == 2 ? g.sCr : 0) + (long long)b * (g.fold == 1 ? g.sCr : 0);
+}
 
 hipError_t launch_gather(const GatherArgs& g, hipStream_t s);
 hipError_t launch_permute(const PermArgs& a, hipStream_t s);

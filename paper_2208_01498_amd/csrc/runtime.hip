@@ -286,8 +286,16 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                 g.sAr = mA ? pA : 0;
                 g.sBr = mB ? pB : 0;
                 g.sCr = g.nr > 1 ? per_r(st.c) : 0;
-                // copies fold into the free index of the only operand that has them
-                g.fold = (g.nr > 1 && mA == 0 && mB == all) ? 1 : (g.nr > 1 && mB == 0 && mA == all) ? 2 : 0;
+                // copies fold into the free index of the operand that has them:
+                // all of them into N (1) or M (2), or, when the two operands
+                // carry disjoint copy bits, A's into M and B's into N (3);
+                // copy bits both operands carry stay an outer batch (0)
+                g.fold = 0;
+                if (g.nr > 1) {
+                    if (mA == 0 && mB == all) g.fold = 1;
+                    else if (mB == 0 && mA == all) g.fold = 2;
+                    else if (mA && mB && (mA & mB) == 0 && (mA | mB) == all) g.fold = 3;
+                }
                 if (mp.scratch_off[si] != std::numeric_limits<size_t>::max())
                     g.P = reinterpret_cast<float2*>(ws + mp.scratch_off[si]);
                 rc = ev_begin();
