@@ -51,6 +51,26 @@ __device__ __forceinline__ size_t pext_u(size_t x, unsigned m) {
     return r;
 }
 
+// Row deposits for a 32-row MFMA output block under a scattered C: row
+// 8*(r/4) + 4*half + r%4 of the block sets row bits 0,1 from r, bit 2 from
+// half and bits 3,4 from r/4; with M >= 32 the block's base row has those
+// five bits clear, so the deposit of the whole row is the base's deposit OR
+// the deposit of the low five bits (the five lowest set bits of cPM).
+struct RowDep {
+    unsigned long long d[5];
+    __device__ void init(unsigned long long pm) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            d[i] = pm & (~pm + 1);
+            pm &= pm - 1;
+        }
+    }
+    __device__ unsigned long long low(int r, int half) const {
+        return ((r & 1) ? d[0] : 0ull) | ((r & 2) ? d[1] : 0ull) | (half ? d[2] : 0ull) |
+               ((r & 4) ? d[3] : 0ull) | ((r & 8) ? d[4] : 0ull);
+    }
+};
+
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
     hi = __float2bfloat16(x);
     lo = __float2bfloat16(x - __bfloat162float(hi));
@@ -344,6 +364,9 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
     const bool part = g.splits > 1;
     float2* Cb = part ? g.P + (((size_t)split * n_outer + outer) * g.nbatch + ib) * (size_t)Mt * Nt
                       : g.C + bb * g.sCb + ib * g.sCi + rr * g.sCr;
+    const bool fastdep = g.scatter && !part && g.M >= 32;
+    RowDep rd;
+    if (fastdep) rd.init(g.cPM);
 #pragma unroll
     for (int i = 0; i < WMF; ++i)
 #pragma unroll
@@ -351,6 +374,9 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
             const int np = n0 + wn + j * 16 + (l32 >> 1);
             if (np >= Nt) continue;
             const int n = np & (g.N - 1);
+            unsigned long long dbase = 0;
+            if (fastdep)
+                dbase = pdep64((unsigned)((m0 + wm + i * 32) & (g.M - 1)), g.cPM) | pdep64((unsigned)n, g.cPN);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int mp = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
@@ -360,7 +386,7 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
                 else {
                     const int m = mp & (g.M - 1);
                     e = (size_t)gemm_c_copy(g, (unsigned)(mp >> lgM), (unsigned)(np >> lgN)) +
-                        (g.transC ? (size_t)n * g.M + m : (size_t)m * g.N + n);
+                        (fastdep ? (size_t)(dbase | rd.low(r, half)) : gemm_c_elem(g, m, n));
                 }
                 reinterpret_cast<float*>(Cb + e)[l32 & 1] = acc[i][j][r];
             }
@@ -608,6 +634,9 @@ k_cgemm3m(GemmArgs g) {
     const bool part = g.splits > 1;
     float2* Cb = part ? g.P + (((size_t)split * n_outer + outer) * g.nbatch + ib) * (size_t)Mt * Nt
                       : g.C + bb * g.sCb + ib * g.sCi + rr * g.sCr;
+    const bool fastdep = g.scatter && !part && g.M >= 32;
+    RowDep rd;
+    if (fastdep) rd.init(g.cPM);
 #pragma unroll
     for (int i = 0; i < WMF; ++i)
 #pragma unroll
@@ -615,6 +644,9 @@ k_cgemm3m(GemmArgs g) {
             const int np = n0 + wn + j * 32 + l32;
             if (np >= Nt) continue;
             const int n = np & (g.N - 1);
+            unsigned long long dbase = 0;
+            if (fastdep)
+                dbase = pdep64((unsigned)((m0 + wm + i * 32) & (g.M - 1)), g.cPM) | pdep64((unsigned)n, g.cPN);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int mp = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
@@ -624,7 +656,7 @@ k_cgemm3m(GemmArgs g) {
                 else {
                     const int m = mp & (g.M - 1);
                     e = (size_t)gemm_c_copy(g, (unsigned)(mp >> lgM), (unsigned)(np >> lgN)) +
-                        (g.transC ? (size_t)n * g.M + m : (size_t)m * g.N + n);
+                        (fastdep ? (size_t)(dbase | rd.low(r, half)) : gemm_c_elem(g, m, n));
                 }
                 const float p1 = acc[i][j][0][r], p2 = acc[i][j][1][r], p3 = acc[i][j][2][r];
                 Cb[e] = make_float2(p1 - p2, p3 - p1 - p2);
@@ -685,7 +717,7 @@ __global__ void __launch_bounds__(256) k_cgemm_dot(GemmArgs g) {
             g.P[(((size_t)split * n_outer + outer) * g.nbatch + ib) * (size_t)MN + o] = v;
         } else {
             float2* C = g.C + bb * g.sCb + ib * g.sCi + rr * g.sCr;
-            C[g.transC ? (size_t)n * M + m : (size_t)m * N + n] = v;
+            C[gemm_c_elem(g, m, n)] = v;
         }
     }
 }
@@ -715,7 +747,7 @@ __global__ void k_reduce_splitk(GemmArgs g) {
         const int m = mp & (g.M - 1), n = np & (g.N - 1);
         const size_t c = bb * g.sCb + ib * g.sCi + rr * g.sCr +
                          (size_t)gemm_c_copy(g, (unsigned)(mp >> lgM), (unsigned)(np >> lgN)) +
-                         (g.transC ? (size_t)n * g.M + m : (size_t)m * g.N + n);
+                         gemm_c_elem(g, m, n);
         g.C[c] = s;
     }
 }
@@ -846,6 +878,7 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
         g.sAb = g0.sBb; g.sAi = g0.sBi; g.sAr = g0.sBr; g.mA = g0.mB;
         g.sBb = g0.sAb; g.sBi = g0.sAi; g.sBr = g0.sAr; g.mB = g0.mA;
         g.transC = !g0.transC;
+        g.cPM = g0.cPN; g.cPN = g0.cPM;
         g.fold = g.fold == 1 ? 2 : g.fold == 2 ? 1 : g.fold;
     }
     g.splits = c.splits;

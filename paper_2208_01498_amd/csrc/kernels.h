@@ -58,6 +58,8 @@ struct GemmArgs {
     long long sAb, sBb, sCb;  // outer strides (elements); 0 = broadcast
     long long sAi, sBi, sCi;  // inner strides
     long long sAr, sBr, sCr;  // slice-block strides; 0 = broadcast
+    int scatter;              // C element (m, n) at pdep(m, cPM) | pdep(n, cPN)
+    unsigned long long cPM, cPN;
 };
 
 // Folded GEMM sizes: the row index m' = a * M + m and column index
@@ -74,6 +76,17 @@ __host__ __device__ inline unsigned pdep_bits(unsigned x, unsigned m) {
     for (; m; m &= m - 1, x >>= 1)
         if (x & 1) r |= m & (~m + 1);
     return r;
+}
+__host__ __device__ inline unsigned long long pdep64(unsigned long long x, unsigned long long m) {
+    unsigned long long r = 0;
+    for (; m; m &= m - 1, x >>= 1)
+        if (x & 1) r |= m & (~m + 1);
+    return r;
+}
+// offset of C element (m, n) within one batch entry
+__host__ __device__ inline size_t gemm_c_elem(const GemmArgs& g, int m, int n) {
+    if (g.scatter) return (size_t)(pdep64((unsigned)m, g.cPM) | pdep64((unsigned)n, g.cPN));
+    return g.transC ? (size_t)n * g.M + m : (size_t)m * g.N + n;
 }
 // element offset of C's copy for folded row block a and column block b
 __host__ __device__ inline long long gemm_c_copy(const GemmArgs& g, unsigned a, unsigned b) {

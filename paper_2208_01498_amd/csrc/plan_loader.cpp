@@ -282,10 +282,27 @@ int parse_plan(const void* blob, size_t nbytes, PlanHost& p) {
         if (slice_eq(st.orderB, nb, kA) && slice_eq(st.orderB, nb + kA.size(), nbB)) st.transB = false;
         else if (slice_eq(st.orderB, nb, nbB) && slice_eq(st.orderB, nb + nbB.size(), kA)) st.transB = true;
         else return fail("B is not [batch][K][N] or [batch][N][K]");
-        // C
+        // C: [batch][M][N], [batch][N][M], or after the batch labels any
+        // interleaving of the M labels (in A's order) with the N labels (in
+        // B's order), written through bit-deposit masks
+        st.scatterC = false;
+        st.cPM = st.cPN = 0;
         if (slice_eq(oc, nb, maA) && slice_eq(oc, nb + maA.size(), nbB)) st.swapC = false;
         else if (slice_eq(oc, nb, nbB) && slice_eq(oc, nb + nbB.size(), maA)) st.swapC = true;
-        else return fail("C is not [batch][M][N] or [batch][N][M]");
+        else {
+            std::vector<int> rest(oc.begin() + nb, oc.end());
+            if (sub(rest, MA) != maA || sub(rest, NB) != nbB)
+                return fail("C is not [batch] followed by M labels in A's order interleaved "
+                            "with N labels in B's order");
+            st.swapC = false;
+            st.scatterC = true;
+            const int rc = (int)rest.size();
+            for (int i = 0; i < rc; ++i) {
+                const uint64_t bit = uint64_t(1) << (rc - 1 - i);
+                if (MA.count(rest[i])) st.cPM |= bit;
+                else st.cPN |= bit;
+            }
+        }
         st.batch_bits = (int)nb;
         st.m_bits = (int)MA.size();
         st.n_bits = (int)NB.size();

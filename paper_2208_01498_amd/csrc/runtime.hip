@@ -277,6 +277,9 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                 g.sAb = hA ? nbat * lenA : 0; g.sAi = lenA;
                 g.sBb = hB ? nbat * lenB : 0; g.sBi = lenB;
                 g.sCb = nbat * M * N; g.sCi = M * N;
+                g.scatter = st.scatterC;
+                g.cPM = st.cPM;
+                g.cPN = st.cPN;
                 g.nbatch = (int)nbat;
                 g.nb = nbC;
                 g.nr = ncopy(st.c);

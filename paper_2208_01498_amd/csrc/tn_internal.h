@@ -63,6 +63,10 @@ struct Step {
     bool hbA = false, hbB = false, hbC = false;
     int batch_bits = 0, m_bits = 0, n_bits = 0, k_bits = 0;
     bool transA = false, transB = false, swapC = false;
+    // C written with its row bits deposited at cPM and column bits at cPN
+    // (element index within one batch entry)
+    bool scatterC = false;
+    uint64_t cPM = 0, cPN = 0;
     uint32_t dep_mask = 0;
     double flops_per_b = 0;         // 8 * 2^(union bits) (times 1 per bitstring)
     // bit permutation maps: dst bit p takes src bit perm[p]

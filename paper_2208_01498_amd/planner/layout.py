@@ -125,9 +125,11 @@ class Layout:
             else:
                 o1 = None
                 new1 = None
+            fresh = set()        # leaves whose order is chosen at this step
             if o1 is None:
                 o1 = self._canonical(None, batch, F1, K, parent.get(nid), l1)
                 leaf_order[t1] = o1
+                fresh.add(t1)
             elif new1 is not None:
                 if t1 == a:
                     permA = new1
@@ -155,6 +157,7 @@ class Layout:
             else:
                 o2 = want_kf
                 leaf_order[t2] = o2
+                fresh.add(t2)
             oa, ob = (o1, o2) if t1 == a else (o2, o1)
             ma = _sub(oa, MA)
             nb = _sub(ob, NB)
@@ -170,10 +173,28 @@ class Layout:
                 bP = lc & lsib & keep_p
                 kP = (lc & lsib) - keep_p
                 fP = lc - lsib
+                fitted = False
                 for o in cands:
                     if _blocks_ok(o, [bP, fP, kP]) or _blocks_ok(o, [bP, kP, fP]):
                         oc = o
+                        fitted = True
                         break
+                if not fitted:
+                    sc = self._scatter(a, b, oa, ob, bo, ma, nb, MA, NB, bP, fP, kP,
+                                       fixed, fresh, permA, permB, hasb, len(lc))
+                    if sc is not None:
+                        oc, oa2, ob2, cost = sc
+                        self.permute_elems += cost
+                        for t, o_old, o_new in ((a, oa, oa2), (b, ob, ob2)):
+                            if o_new == o_old:
+                                continue
+                            if t in fresh:
+                                leaf_order[t] = o_new
+                            elif t == a:
+                                permA = o_new
+                            else:
+                                permB = o_new
+                        oa, ob = oa2, ob2
             lc = batch | MA | NB
             for l in lc:
                 cnt[l] = cnt.get(l, 0) + 1
@@ -188,6 +209,43 @@ class Layout:
             if i not in leaf_order:
                 leaf_order[i] = labels[i]
         return leaf_order, out
+
+    def _scatter(self, a, b, oa, ob, bo, ma, nb, MA, NB, bP, fP, kP, fixed, fresh,
+                 permA, permB, hasb, rank_c):
+        """An output order that the parent step can use without a permute,
+        written by the GEMM as an interleaving of its row and column index
+        bits: C = bo + [bP - bo] + X + Y with {X, Y} = {fP, kP}, the M labels
+        in A's order and the N labels in B's order.  A or B is re-sorted
+        (stable, by block) when its own order does not list its labels
+        block by block; returns None when that costs more than permuting C
+        or when the step's batch labels are not all parent batch labels."""
+        if not set(bo) <= bP:
+            return None
+        size = lambda t, n: 2.0 ** n * (64 if hasb[t] else 1)
+        c_cost = 2.0 ** rank_c * (64 if (hasb[a] or hasb[b]) else 1)
+        best = None
+        for X, Y in ((fP, kP), (kP, fP)):
+            blocks = [bP - set(bo), X, Y]
+            blk = lambda l: next(i for i, s_ in enumerate(blocks) if l in s_)
+            ma2 = sorted(ma, key=blk)
+            nb2 = sorted(nb, key=blk)
+            cost = 0.0
+            for t, o, old_sub, new_sub, already in ((a, oa, ma, ma2, permA is not None),
+                                                    (b, ob, nb, nb2, permB is not None)):
+                if old_sub != new_sub and t not in fresh and not already:
+                    cost += size(t, len(o))
+            if cost >= c_cost:
+                continue
+            oc = list(bo)
+            for s_ in blocks:
+                oc += [l for l in ma2 if l in s_] + [l for l in nb2 if l in s_]
+            if best is None or cost < best[3]:
+                it = iter(ma2)
+                oa2 = [next(it) if l in MA else l for l in oa]
+                it = iter(nb2)
+                ob2 = [next(it) if l in NB else l for l in ob]
+                best = (oc, oa2, ob2, cost)
+        return best
 
     def _free_order(self, F, cur, pinfo):
         return sorted(F)

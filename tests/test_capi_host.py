@@ -84,3 +84,43 @@ def test_rejects_label_out_of_range(B, blob):
     bad = bytearray(blob)
     struct.pack_into("<I", bad, off, n_labels + 5)
     _rejects(B, bytes(bad))
+
+
+def _scattered_step(plan):
+    """Index of a step whose output order interleaves its row and column
+    labels, and that step's (A order, B order)."""
+    order = {i: plan.leaf_order[i] for i in range(len(plan.net.factors))}
+    nid = len(plan.net.factors)
+    for si, ((a, b), lay) in enumerate(zip(plan.steps, plan.step_layout)):
+        oa = lay["permA"] or order[a]
+        ob = lay["permB"] or order[b]
+        MA, NB = set(oa) - set(ob), set(ob) - set(oa)
+        rest = [l for l in lay["c_order"] if l in MA or l in NB]
+        ma = [l for l in oa if l in MA]
+        nb = [l for l in ob if l in NB]
+        if rest != ma + nb and rest != nb + ma and len(ma) >= 2:
+            return si, ma
+        order[nid] = lay["c_order"]
+        nid += 1
+    return None, None
+
+
+def test_interleaved_output_order(B):
+    """An output order that interleaves the row labels (in A's order) with
+    the column labels (in B's order) is accepted; the same order with two
+    row labels exchanged is not a bit deposit of the GEMM's row index and
+    is rejected with the loader's message for it."""
+    circ, _, _ = make_config("cfg1")
+    plan = make_plan(circ, n_slices=0, B=8)
+    si, ma = _scattered_step(plan)
+    assert si is not None, "planner produced no interleaved output order"
+    B.tn_plan_validate(plan.to_blob())
+    oc = plan.step_layout[si]["c_order"]
+    i, j = oc.index(ma[0]), oc.index(ma[1])
+    bad = list(oc)
+    bad[i], bad[j] = bad[j], bad[i]
+    plan.step_layout[si]["c_order"] = bad
+    with pytest.raises(B.TnError) as e:
+        B.tn_plan_validate(plan.to_blob())
+    assert e.value.code == B.TN_EINVAL
+    assert "interleaved" in str(e.value)
