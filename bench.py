@@ -5,7 +5,7 @@ dominant GEMM kernel and the CPU oracle timed beside it.
 One step = one tn_contract_amplitudes call over the whole batch (all slices,
 all chunks), inputs resident: the plan is built and loaded before timing.
 
-  python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3]
+  python bench.py [--steps K] [--warmup W] [--precision fp32_3m|fp32|bf16x3]
                   [--config cfg3] [--batch B] [--slices S] [--width W]
                   [--no-cpu]
 
@@ -28,20 +28,19 @@ PEAK = {"fp32": 157.3e12, "fp32_3m": 157.3e12, "bf16x3": 2516.6e12}
 EXEC = {"fp32": 1.0, "fp32_3m": 0.75, "bf16x3": 3.0}
 
 # HBM traffic per launch of a kernel class, from two rocprofv3 --pmc passes
-# (FETCH_SIZE, WRITE_SIZE) over `bench.py --batch 3 --warmup 0 --steps 1
-# --no-cpu`, each scaled by the counter's reading for a plain 1 GiB device
+# (FETCH_SIZE, WRITE_SIZE) over `bench.py --batch 6 --warmup 0 --steps 1
+# --no-cpu` (one chunk, the launch shapes of the default run), each scaled
+# by the counter's reading for a plain 1 GiB device
 # copy (`bench.py --copy-calibration`).  Keyed by the SHA-256 of the kernel's
 # source file: a changed kernel reports null until it is measured again.
-TRAFFIC = {
-    "cgemm_mfma_128x128": {
-        "source": "gemm.hip",
-        "source_sha256": "f6c66bfa8902d85df19a6fbac68b01c1f2d8102a45e5b506dc3b2fb9e8473cd7",
-        "precision": "fp32",
-        "bytes_per_launch": 4.716e10,
-        "note": "HBM fetch 3.643e10 + write 1.073e10 bytes per launch (44 launches, copy-scaled "
-                "FETCH_SIZE x2.0, WRITE_SIZE x1.0); algorithmic 2.000e10",
-    },
-}
+TRAFFIC = [
+    {"class": "cgemm_mfma_128x128", "precision": "fp32_3m", "source": "gemm.hip",
+     "source_sha256": "c8f98b1cc68f8e191bf886b73f8d85c40d0538b2e308c9d7a68389338cb246c1",
+     "bytes_per_launch": 1.180e11,
+     "note": "HBM fetch 9.615e10 + write 2.187e10 bytes per launch (48 launches of a chunk of 6 "
+             "bitstrings; FETCH_SIZE x2.0 and WRITE_SIZE x1.0 from a 1 GiB copy); algorithmic "
+             "3.741e10"},
+]
 
 
 def source_hash(name):
@@ -202,7 +201,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="cfg3")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_3m", "bf16x3"])
+    ap.add_argument("--precision", default="fp32_3m", choices=["fp32", "fp32_3m", "bf16x3"])
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--slices", type=int, default=10)
     ap.add_argument("--width", type=float, default=None)
@@ -285,10 +284,17 @@ def main():
                 "algorithmic_tflops": alg / 1e12,
                 "avg_launch_ms": ms / max(1, prof["launches"][dom]),
                 "gemm_time_frac": sum(prof["time_ms"][:4]) / max(1e-9, sum(prof["time_ms"]))}
-    rec = TRAFFIC.get(kinds[dom])
-    if rec and rec["source_sha256"] == source_hash(rec["source"]) and rec["precision"] == args.precision:
-        roofline["traffic"] = rec["bytes_per_launch"]
-        roofline["traffic_note"] = rec["note"]
+    # the permute kernels against HBM (algorithmic bytes: one read and one
+    # write of every element)
+    pm = prof["time_ms"][4]
+    permute = {"bound": "hbm", "achieved": prof["bytes"][4] / (pm * 1e-3) / 1e9 if pm > 0 else 0.0,
+               "peak": 8000.0, "unit": "GB/s", "launches": prof["launches"][4], "ms": pm}
+    permute["frac"] = permute["achieved"] / permute["peak"]
+    for rec in TRAFFIC:
+        if (rec["class"] == kinds[dom] and rec["precision"] == args.precision and
+                rec["source_sha256"] == source_hash(rec["source"])):
+            roofline["traffic"] = rec["bytes_per_launch"]
+            roofline["traffic_note"] = rec["note"]
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(circ, int(words[0]), seconds=args.cpu_seconds)
@@ -307,6 +313,7 @@ def main():
                    "algorithmic_flops_per_amplitude": st["algorithmic_flops"] / nb},
         "roofline": roofline,
         "achieved_algorithmic_tflops": st["algorithmic_flops"] * args.steps / el / 1e12,
+        "permute_roofline": permute,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

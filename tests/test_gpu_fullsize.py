@@ -91,3 +91,44 @@ def test_iqp48_vs_closed_form(eng):
     err = (np.abs(got - ref) / np.maximum(np.abs(ref), 2.0 ** (-circ.n / 2))).max()
     print("max err", err, "max plain relative", (np.abs(got - ref) / np.abs(ref)).max(), flush=True)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-5), (1, 1e-5), (2, 1e-3)])
+def test_mirror_6x6_fsim_depth12_shape(eng, prec, tol):
+    """C^dag C for a 6x6 depth-6 sqrt(X/Y/W) + fSim(pi/2, pi/6) circuit (the
+    depth-12 network shape of the 6x6 fSim workload), sliced so that no
+    per-slice intermediate exceeds rank 28: a(0) = 1 and a(x != 0) = 0."""
+    from paper_2208_01498_amd.planner.plan import make_plan
+    c = mirror(lattice_circuit(6, 6, 6, 2000, "sqrt", "fsim"))
+    words = np.concatenate([[0], random_bitstrings(36, 3, 2001)]).astype(np.uint64)
+    print("case mirror 6x6 fsim d6+inverse, prec", prec, flush=True)
+    plan = make_plan(c, n_slices=None, target_width=28, B=len(words))
+    assert plan.stats["max_bits"] <= 28
+    got = eng.amplitudes(eng.load(plan.to_blob()), words, prec)
+    print("a(0) - 1 =", got[0] - 1, "max |a(x!=0)| =", np.abs(got[1:]).max(), flush=True)
+    assert abs(got[0] - 1) <= tol
+    assert np.abs(got[1:]).max() <= tol
+
+
+def test_fsim_6x6_depth12_precisions_agree(eng):
+    """The 6x6 depth-12 fSim workload itself (max per-slice rank 28) on 2 of
+    its 256 bitstrings: FP32 4M and 3M agree within twice the FP32
+    tolerance, split-bf16 within 1e-3."""
+    from paper_2208_01498_amd import binding as B
+    from paper_2208_01498_amd.planner.plan import make_plan
+    circ, words, _ = make_config("cfg2")
+    words = words[:2]
+    print("case cfg2 2 bitstrings", flush=True)
+    plan = make_plan(circ, n_slices=None, target_width=28, B=len(words))
+    assert plan.stats["max_bits"] <= 28
+    p = eng.load(plan.to_blob())
+    a = eng.amplitudes(p, words, B.TN_FP32_4M)
+    c = eng.amplitudes(p, words, B.TN_FP32_3M)
+    b = eng.amplitudes(p, words, B.TN_SPLIT_BF16)
+    scale = 2.0 ** (-circ.n / 2)
+    r3 = np.abs(a - c) / np.maximum(np.abs(a), scale)
+    rb = np.abs(a - b) / np.maximum(np.abs(a), scale)
+    print("4M vs 3M", r3.max(), "4M vs bf16x3", rb.max(), "2^n |a|^2", (2.0 ** circ.n) * np.abs(a) ** 2,
+          flush=True)
+    assert r3.max() <= 2e-5
+    assert rb.max() <= 1e-3
