@@ -274,16 +274,22 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
             } else {
                 uint32_t* bh = reinterpret_cast<uint32_t*>(Bh + buf * 2 * BN * RA);
                 uint32_t* bl = reinterpret_cast<uint32_t*>(Bl + buf * 2 * BN * RA);
-                // real column 2n: rows (2k, 2k+1) = (Br, -Bi); column 2n+1: (Bi, Br)
-                uint32_t h, l;
-                split2(rb[i].x, -rb[i].y, h, l);
-                bh[((2 * n) * RA + 2 * k) / 2] = h; bl[((2 * n) * RA + 2 * k) / 2] = l;
-                split2(rb[i].y, rb[i].x, h, l);
-                bh[((2 * n + 1) * RA + 2 * k) / 2] = h; bl[((2 * n + 1) * RA + 2 * k) / 2] = l;
-                split2(rb[i].z, -rb[i].w, h, l);
-                bh[((2 * n2) * RA + 2 * k2) / 2] = h; bl[((2 * n2) * RA + 2 * k2) / 2] = l;
-                split2(rb[i].w, rb[i].z, h, l);
-                bh[((2 * n2 + 1) * RA + 2 * k2) / 2] = h; bl[((2 * n2 + 1) * RA + 2 * k2) / 2] = l;
+                // real column 2n: rows (2k, 2k+1) = (Br, -Bi); column 2n+1:
+                // (Bi, Br).  Each real is split once; the negated halves of
+                // -Bi are the halves of Bi with the sign bit flipped (exact)
+                uint32_t h0, l0, h1, l1;
+                split2(rb[i].x, rb[i].y, h0, l0);       // (Br, Bi) of element 0
+                split2(rb[i].z, rb[i].w, h1, l1);       // element 1
+                auto neg_hi = [](uint32_t v) {           // (r, i) -> (r, -i)
+                    return v ^ 0x80000000u;
+                };
+                auto swap = [](uint32_t v) {             // (r, i) -> (i, r)
+                    return (v >> 16) | (v << 16);
+                };
+                bh[((2 * n) * RA + 2 * k) / 2] = neg_hi(h0); bl[((2 * n) * RA + 2 * k) / 2] = neg_hi(l0);
+                bh[((2 * n + 1) * RA + 2 * k) / 2] = swap(h0); bl[((2 * n + 1) * RA + 2 * k) / 2] = swap(l0);
+                bh[((2 * n2) * RA + 2 * k2) / 2] = neg_hi(h1); bl[((2 * n2) * RA + 2 * k2) / 2] = neg_hi(l1);
+                bh[((2 * n2 + 1) * RA + 2 * k2) / 2] = swap(h1); bl[((2 * n2 + 1) * RA + 2 * k2) / 2] = swap(l1);
             }
         }
     };
