@@ -54,6 +54,9 @@ extern "C" {
 #define TN_SPLIT_BF16 2     /* x = hi + lo in bf16, hi*hi + hi*lo + lo*hi, FP32 acc */
 #define TN_SPLIT_FP16 3     /* reserved: fp16 halves with power-of-two scaling;
                                rejected with TN_EINVAL */
+#define TN_BF16_1TERM 4     /* operands rounded once to bf16, one product per
+                               complex product, FP32 accumulation: the plain
+                               rounding reference point for the split mode */
 
 typedef struct tn_ctx tn_ctx;
 typedef struct tn_plan tn_plan;
@@ -205,7 +208,8 @@ int tn_last_exec_stats(tn_ctx* ctx, tn_exec_stats* out);
  *   A(m,k) = A[ob*sAb + ib*sAi + (transA ? k*M + m : m*K + k)]
  *   B(k,n) = B[ob*sBb + ib*sBi + (transB ? n*K + k : k*N + n)]
  *   strides in complex elements; sAb or sBb may be 0 (broadcast); M, N, K
- *   powers of two.  precision TN_FP32_4M, TN_FP32_3M or TN_SPLIT_BF16.  `scratch`:
+ *   powers of two.  precision TN_FP32_4M, TN_FP32_3M, TN_SPLIT_BF16 or
+ *   TN_BF16_1TERM.  `scratch`:
  *   device memory for split-K partial sums (see
  *   tn_kernel_cgemm_scratch_bytes).  Returns TN_EINVAL for bad sizes or too
  *   little scratch, TN_EDEVICE on a launch error.

@@ -15,9 +15,9 @@ LIB_PATH = os.path.join(HERE, "libtnamp.so")
 
 TN_OK, TN_PENDING = 0, 1
 TN_EINVAL, TN_ENOMEM, TN_EBUSY, TN_EDEVICE, TN_ECANCELLED, TN_ENOTFOUND = -1, -2, -3, -4, -5, -6
-TN_FP32_4M, TN_FP32_3M, TN_SPLIT_BF16, TN_SPLIT_FP16 = 0, 1, 2, 3
+TN_FP32_4M, TN_FP32_3M, TN_SPLIT_BF16, TN_SPLIT_FP16, TN_BF16_1TERM = 0, 1, 2, 3, 4
 PRECISIONS = {"fp32": TN_FP32_4M, "fp32_3m": TN_FP32_3M, "bf16x3": TN_SPLIT_BF16,
-              "fp16x3": TN_SPLIT_FP16}
+              "fp16x3": TN_SPLIT_FP16, "bf16x1": TN_BF16_1TERM}
 
 EXPORTED = ["tn_ctx_create", "tn_ctx_destroy", "tn_plan_load", "tn_plan_validate",
             "tn_plan_info", "tn_plan_unload", "tn_contract_amplitudes", "tn_submit",

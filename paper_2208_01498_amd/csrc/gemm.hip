@@ -12,6 +12,8 @@
 //                   split x = hi + lo when staged into LDS, and
 //                   hi*hi + hi*lo + lo*hi are accumulated in FP32; one MFMA is
 //                   32 x 16 x 8 (complex)
+//   k_cgemm<4,...>  the same with hi*hi only (plain bf16 rounding of the
+//                   operands), kept as the lower-accuracy reference point
 //   k_cgemm3m       FP32 3M on the same MFMA used as a real 32 x 32 x 2
 //                   product: three real products per complex product
 //                   (6 MNK executed flops instead of 8 MNK)
@@ -346,8 +348,10 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
                 for (int i = 0; i < WMF; ++i)
 #pragma unroll
                     for (int j = 0; j < WNF; ++j) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], yh[j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yl[j], acc[i][j], 0, 0, 0);
+                        if constexpr (PREC == 2) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], yh[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yl[j], acc[i][j], 0, 0, 0);
+                        }
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yh[j], acc[i][j], 0, 0, 0);
                     }
             }
@@ -858,6 +862,7 @@ static void launch_cfg3(const GemmArgs& g, size_t grid, hipStream_t s) {
 template <int WGM, int WGN, int WMF, int WNF>
 static void launch_prec(const GemmArgs& g, int precision, size_t grid, hipStream_t s) {
     if (precision == 2) launch_cfg<2, WGM, WGN, WMF, WNF>(g, grid, s);
+    else if (precision == 4) launch_cfg<4, WGM, WGN, WMF, WNF>(g, grid, s);
     else launch_cfg<0, WGM, WGN, WMF, WNF>(g, grid, s);
 }
 

@@ -446,7 +446,8 @@ int tn_contract_amplitudes(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bit
                            int32_t precision, void* hip_stream, double* out_re_im) {
     if (!ctx || !plan || !bits || !out_re_im) { set_error("null argument"); return TN_EINVAL; }
     if (nb <= 0) { set_error("nb must be positive"); return TN_EINVAL; }
-    if (precision != TN_FP32_4M && precision != TN_FP32_3M && precision != TN_SPLIT_BF16) {
+    if (precision != TN_FP32_4M && precision != TN_FP32_3M && precision != TN_SPLIT_BF16 &&
+        precision != TN_BF16_1TERM) {
         set_error("precision mode not available");
         return TN_EINVAL;
     }
@@ -504,7 +505,8 @@ int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N,
         set_error("gemm needs " + std::to_string(need) + " bytes of scratch");
         return TN_EINVAL;
     }
-    if (precision != TN_FP32_4M && precision != TN_FP32_3M && precision != TN_SPLIT_BF16) { set_error("precision mode not available"); return TN_EINVAL; }
+    if (precision != TN_FP32_4M && precision != TN_FP32_3M && precision != TN_SPLIT_BF16 &&
+        precision != TN_BF16_1TERM) { set_error("precision mode not available"); return TN_EINVAL; }
     GemmArgs g{};
     g.A = static_cast<const float2*>(A);
     g.B = static_cast<const float2*>(B);

@@ -252,7 +252,8 @@ int tn_submit(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int32_t nb
               uint64_t* ticket) {
     if (!ctx || !plan || !bits || !ticket) { set_error("null argument"); return TN_EINVAL; }
     if (nb <= 0) { set_error("nb must be positive"); return TN_EINVAL; }
-    if (precision != TN_FP32_4M && precision != TN_FP32_3M && precision != TN_SPLIT_BF16) { set_error("precision mode not available"); return TN_EINVAL; }
+    if (precision != TN_FP32_4M && precision != TN_FP32_3M && precision != TN_SPLIT_BF16 &&
+        precision != TN_BF16_1TERM) { set_error("precision mode not available"); return TN_EINVAL; }
     if (ctx->poisoned) { set_error("context poisoned"); return TN_EDEVICE; }
     for (int i = 0; i < nb; ++i)
         if (bits[i] & ~plan->host.out_mask) { set_error("bitstring has a bit at a position >= n_qubits"); return TN_EINVAL; }

@@ -132,3 +132,22 @@ def test_fsim_6x6_depth12_precisions_agree(eng):
           flush=True)
     assert r3.max() <= 2e-5
     assert rb.max() <= 1e-3
+
+
+def test_plain_bf16_rounding_is_the_weaker_reference(eng):
+    """The split mode against plain bf16 rounding of the operands (one
+    product per complex product) on the 4x5 depth-16 Haar + CZ circuit, 2^6
+    slices: the split result meets 1e-3 and is more accurate than plain
+    rounding, whose error is reported."""
+    from paper_2208_01498_amd import binding as B
+    c = lattice_circuit(4, 5, 16, 3010, "haar", "cz")
+    words = random_bitstrings(20, 32, 3011)
+    plan = _plan(c, 6, len(words))
+    p = eng.load(plan.to_blob())
+    ref = statevector_amplitudes(c, words)
+    scale = np.maximum(np.abs(ref), 2.0 ** (-c.n / 2))
+    e3 = (np.abs(eng.amplitudes(p, words, B.TN_SPLIT_BF16) - ref) / scale).max()
+    e1 = (np.abs(eng.amplitudes(p, words, B.TN_BF16_1TERM) - ref) / scale).max()
+    print("max err: bf16 hi/lo three products %.3e, plain bf16 one product %.3e" % (e3, e1), flush=True)
+    assert e3 <= 1e-3
+    assert e1 > e3
