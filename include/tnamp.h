@@ -101,6 +101,12 @@ int tn_ctx_destroy(tn_ctx* ctx);
  * tn_plan_load: copy and validate a TNP1 blob (written by the plan builder),
  * convert leaves from complex128 to complex64 (round to nearest even) and
  * upload them.  The plan stays resident until unloaded.
+ * A blob with header flag bit 0 set is a projector plan: the network of C
+ * and its complex conjugate for the quantity <0|C^dag (x)_q P_q C|0> (the
+ * problem statement around Theorem 2), with P_q = |x_q><x_q| on qubits that
+ * carry output labels (two per qubit, one in each layer) and P_q = 1 on the
+ * others (no output label; their bitstring bits must be 0).  Contracting it
+ * returns that value for each bitstring in place of an amplitude.
  * Errors: TN_EINVAL (malformed blob: bad magic/version, truncated, label out
  * of range, dimension other than 2, operand used twice, step orders that do
  * not form a batched GEMM), TN_EDEVICE.
@@ -116,7 +122,8 @@ int tn_plan_info(const tn_plan* plan, tn_plan_info_t* out);
 int tn_plan_unload(tn_ctx* ctx, tn_plan* plan);
 
 /*
- * tn_contract_amplitudes: blocking.  bits[nb] -> out_re_im[2*nb].
+ * tn_contract_amplitudes: blocking.  bits[nb] -> out_re_im[2*nb]: the
+ * amplitudes <x|C|0>, or for a projector plan <0|C^dag (x)_q P_q C|0>.
  *   precision   one of the TN_* precision modes.
  *   hip_stream  a hipStream_t to run on, or NULL for the context's stream.
  * The batch is processed in chunks sized to the arena.

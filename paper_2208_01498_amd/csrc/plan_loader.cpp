@@ -87,7 +87,9 @@ int parse_plan(const void* blob, size_t nbytes, PlanHost& p) {
     if (version != 1) return fail("unsupported version");
     uint32_t n_qubits = r.u32(), n_labels = r.u32(), n_leaves = r.u32(), n_steps = r.u32(),
              n_sliced = r.u32();
-    r.u32();  // flags
+    const uint32_t flags = r.u32();  // bit 0: U and its conjugate (projector mode)
+    if (flags & ~1u) return fail("unknown flags");
+    const bool doubled = (flags & 1u) != 0;
     double sre = r.f64(), sim = r.f64();
     if (!r.ok) return fail("truncated header");
     if (n_qubits == 0 || n_qubits > (uint32_t)kMaxQubits) return fail("qubit count out of range");
@@ -98,7 +100,7 @@ int parse_plan(const void* blob, size_t nbytes, PlanHost& p) {
     p.n_qubits = (int)n_qubits;
     p.scale = {sre, sim};
     p.labels.resize(n_labels);
-    std::vector<int> out_of_qubit(n_qubits, -1);
+    std::vector<int> outs_of_qubit(n_qubits, 0);
     for (uint32_t i = 0; i < n_labels; ++i) {
         LabelInfo& L = p.labels[i];
         L.dim = r.u8();
@@ -111,8 +113,11 @@ int parse_plan(const void* blob, size_t nbytes, PlanHost& p) {
         if (L.kind > 1) return fail("bad label kind");
         if (L.kind == 1) {
             if (L.qubit < 0 || L.qubit >= (int)n_qubits) return fail("output label qubit out of range");
-            if (out_of_qubit[L.qubit] >= 0) return fail("two output labels on one qubit");
-            out_of_qubit[L.qubit] = (int)i;
+            // one output label per qubit; two (U and its conjugate) in
+            // projector mode
+            if (++outs_of_qubit[L.qubit] > (doubled ? 2 : 1))
+                return fail(doubled ? "more than two output labels on one qubit"
+                                    : "two output labels on one qubit");
             p.out_mask |= (1ull << L.qubit);
         }
     }
@@ -342,7 +347,9 @@ int parse_plan(const void* blob, size_t nbytes, PlanHost& p) {
     if (p.rank[p.root] != 0) return fail("the last step must leave no labels");
     for (int t = 0; t < T - 1; ++t)
         if (!used[t]) return fail("tensor never consumed");
-    if (p.out_mask != ((n_qubits == 64) ? ~0ull : ((1ull << n_qubits) - 1)))
+    // amplitudes project every qubit; in projector mode a traced qubit has
+    // no output label (its bitstring bit must be 0)
+    if (!doubled && p.out_mask != ((n_qubits == 64) ? ~0ull : ((1ull << n_qubits) - 1)))
         return fail("every qubit needs an output label");
     p.flops_per_slice_per_b = fps;
     p.flops_total_per_b = ftot;

@@ -61,6 +61,7 @@ class Network:
         self.scale = scale            # complex
         self.positions = positions    # qubit coordinates
         self.out_label = {l.qubit: l.id for l in labels.values() if l.kind == "out"}
+        self.doubled = False          # U and its conjugate (projector mode)
 
     def label_users(self):
         users = {}
@@ -168,6 +169,42 @@ def build_network(circ, simplify=True, swap_relabel=False, coarsen=0):
         if coarsen:
             coarsen_network(net, coarsen)
     _attach_scalar_gates(net, circ, scalar_gates)
+    return net
+
+
+def build_doubled_network(circ, traced=(), simplify=True):
+    """The paper's quantity c = <0|U^dag (x)_q P_q U|0> for product
+    projectors (the problem statement around Theorem 2): the network of U
+    and its complex conjugate, with P_q = |x_q><x_q| on the qubits not in
+    `traced` (both output indices of qubit q are fixed to x_q at run time)
+    and P_q = 1 on the qubits in `traced` (the two output indices become one
+    summed index).  With no qubit traced, c(x) = |<x|C|0>|^2; tracing a set
+    of qubits gives the marginal probability of the others.  Gate ids of the
+    conjugate layer are offset by the number of gates."""
+    traced = set(int(q) for q in traced)
+    one = build_network(circ, simplify=simplify)
+    off = max(one.labels) + 1
+    G = len(circ.gates)
+    labels = {}
+    for l, L in one.labels.items():
+        labels[l] = Label(l, L.dim, L.kind, L.qubit, L.gate)
+        labels[l + off] = Label(l + off, L.dim, L.kind, L.qubit, L.gate + G if L.gate >= 0 else L.gate)
+    out1 = {L.qubit: l for l, L in one.labels.items() if L.kind == "out"}
+    ren = {}
+    for q in traced:
+        o = out1[q]
+        ren[o + off] = o
+        labels[o].kind = "wire"
+        del labels[o + off]
+    factors = [Factor(f.data.copy(), f.labels, f.gates, f.pos, f.weight) for f in one.factors]
+    for f in one.factors:
+        factors.append(Factor(np.conj(f.data), [ren.get(l + off, l + off) for l in f.labels],
+                              {g + G for g in f.gates}, f.pos, f.weight))
+    scale = one.scale * np.conj(one.scale)
+    net = Network(circ.n, labels, factors, complex(scale), circ.positions)
+    net.doubled = True
+    if simplify:
+        simplify_network(net)
     return net
 
 

@@ -66,8 +66,9 @@ class Plan:
         remap = {l: i for i, l in enumerate(used)}
         out = bytearray()
         out += MAGIC
+        flags = 1 if getattr(net, "doubled", False) else 0
         out += struct.pack("<7I", VERSION, net.n_qubits, len(used), len(net.factors),
-                           len(self.steps), len(self.sliced), 0)
+                           len(self.steps), len(self.sliced), flags)
         out += struct.pack("<2d", net.scale.real, net.scale.imag)
         for l in used:
             lab = net.labels[l]
@@ -102,17 +103,22 @@ class Plan:
 
 
 def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
-              n_circles=24, trials=1, objective="time", coarsen=0):
+              n_circles=24, trials=1, objective="time", coarsen=0, projector=None):
     """Build a plan.  ``n_slices``: number of sliced labels (log2 of the slice
     count), or None to slice until the widest per-slice intermediate is at
-    most ``target_width`` (log2 elements, batch included)."""
-    from .network import _is_swap_diag
+    most ``target_width`` (log2 elements, batch included).  ``projector``:
+    None for amplitudes <x|C|0>; otherwise the set of traced qubits of the
+    projector quantity <0|C^dag (x)_q P_q C|0> (P_q = |x_q><x_q| elsewhere)."""
+    from .network import _is_swap_diag, build_doubled_network
     forms = [False]
-    if any(len(g.qubits) == 2 and _is_swap_diag(g.matrix) for g in circ.gates):
+    if projector is None and any(len(g.qubits) == 2 and _is_swap_diag(g.matrix) for g in circ.gates):
         forms.append(True)
     best = None
     for swap_relabel in forms:
-        net = build_network(circ, swap_relabel=swap_relabel, coarsen=coarsen)
+        if projector is None:
+            net = build_network(circ, swap_relabel=swap_relabel, coarsen=coarsen)
+        else:
+            net = build_doubled_network(circ, traced=projector)
         for t in range(trials):
             tb = TreeBuilder(net, np.random.Generator(np.random.PCG64(seed + t)),
                              bottom=bottom, n_circles=n_circles)

@@ -192,3 +192,42 @@ def test_slice_block_is_bitwise_invariant():
             assert _relerr(a, ref, circ.n).max() <= TOL[prec]
     finally:
         eng.close()
+
+
+def _projectors(n, word, traced):
+    P = []
+    for q in range(n):
+        if q in traced:
+            P.append(np.eye(2))
+        else:
+            e = np.zeros((2, 2))
+            e[(int(word) >> q) & 1, (int(word) >> q) & 1] = 1.0
+            P.append(e)
+    return P
+
+
+@pytest.mark.parametrize("traced", [(), (0, 5, 11), tuple(range(2, 12))])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_projector_mode_vs_doubled_oracle(eng, traced, prec):
+    """The paper's quantity <0|C^dag (x)_q P_q C|0> (P_q = |x_q><x_q| on
+    projected qubits, 1 on traced ones) through the same executor, against
+    the oracle's doubled expectation; tracing all but two qubits, the four
+    marginal probabilities sum to 1."""
+    from oracle import doubled_expectation
+    circ = lattice_circuit(3, 4, 6, 460, "haar", "cz")
+    mask = sum(1 << q for q in traced)
+    if len(traced) == circ.n - 2:
+        free = [q for q in range(circ.n) if q not in traced]
+        words = np.array([(a << free[0]) | (b << free[1]) for a in (0, 1) for b in (0, 1)], dtype=np.uint64)
+    else:
+        words = np.array([int(w) & ~mask for w in random_bitstrings(circ.n, 9, 461)], dtype=np.uint64)
+    print("case projector traced", traced, "prec", prec, flush=True)
+    plan = _plan(circ, 2, B=len(words), projector=traced)
+    got = eng.amplitudes(eng.load(plan.to_blob()), words, prec)
+    ref = np.array([doubled_expectation(circ, _projectors(circ.n, w, traced), method="statevector")
+                    for w in words])
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), 2.0 ** (-(circ.n - len(traced))))
+    print("max err", err.max(), flush=True)
+    assert err.max() <= TOL[prec]
+    if len(traced) == circ.n - 2:
+        assert abs(got.sum() - 1) <= 1e-5

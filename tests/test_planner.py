@@ -198,3 +198,78 @@ def test_swap_form_network_matches_statevector():
     got = np.array([_contract_plan_network(plan, w) for w in words])
     ref = statevector_amplitudes(circ, words)
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def _contract_net_host(net, steps, word):
+    """Dense FP64 contraction of a planner network in a plan's order, output
+    labels fixed to the bits of `word` (test helper)."""
+    from oracle.pairwise import contract_pair
+    live = {}
+    for i, f in enumerate(net.factors):
+        d, ls = f.data, list(f.labels)
+        idx = tuple(((int(word) >> net.labels[l].qubit) & 1) if net.labels[l].kind == "out"
+                    else slice(None) for l in ls)
+        live[i] = (d[idx], [l for l in ls if net.labels[l].kind != "out"])
+    nid = len(net.factors)
+    for a, b in steps:
+        A, la = live.pop(a)
+        B, lb = live.pop(b)
+        others = set(l for _, ls in live.values() for l in ls)
+        keep = set(l for l in set(la) | set(lb) if l in others)
+        live[nid] = contract_pair(A, la, B, lb, keep)
+        nid += 1
+    (arr, ls), = live.values()
+    return complex(np.asarray(arr).sum()) * net.scale
+
+
+def _projectors(n, word, traced):
+    P = []
+    for q in range(n):
+        if q in traced:
+            P.append(np.eye(2))
+        else:
+            e = np.zeros((2, 2))
+            e[(int(word) >> q) & 1, (int(word) >> q) & 1] = 1.0
+            P.append(e)
+    return P
+
+
+@pytest.mark.parametrize("traced", [(), (0, 5), (1, 2, 3, 7, 9)])
+def test_projector_network_matches_doubled_oracle(traced):
+    """The planner's network of C and its conjugate (the paper's
+    <0|C^dag (x) P_q C|0>) contracted in the plan's order equals the oracle's
+    doubled expectation, for projected and traced qubits."""
+    from oracle import doubled_expectation
+    circ = lattice_circuit(3, 4, 5, 450, "haar", "cz")
+    plan = make_plan(circ, n_slices=0, B=2, projector=traced)
+    for w in random_bitstrings(circ.n, 3, 451):
+        w = int(w) & ~sum(1 << q for q in traced)
+        got = _contract_net_host(plan.net, plan.steps, w)
+        ref = doubled_expectation(circ, _projectors(circ.n, w, traced), method="statevector")
+        assert abs(got - ref) <= 1e-12 * max(abs(ref), 1e-300)
+
+
+def test_projector_marginals_sum_to_one():
+    """Tracing all but two qubits gives a distribution over their four
+    values: the four planner-network values sum to 1."""
+    circ = lattice_circuit(2, 3, 4, 452, "haar", "cz")
+    traced = (1, 2, 3, 4)
+    plan = make_plan(circ, n_slices=0, B=4, projector=traced)
+    tot = sum(_contract_net_host(plan.net, plan.steps, w) for w in (0b000000, 0b000001, 0b100000, 0b100001))
+    assert abs(tot - 1) <= 1e-12
+
+
+def test_projector_blob_accepted_and_amplitude_blob_rules_kept():
+    from paper_2208_01498_amd import binding as B
+    B.load_library()
+    circ = lattice_circuit(3, 3, 4, 453, "haar", "cz")
+    info = B.tn_plan_validate(make_plan(circ, B=2, projector=(0, 4)).to_blob())
+    assert info["n_steps"] == info["n_leaves"] - 1
+    # the same two-outputs-per-qubit network without the projector flag is
+    # rejected
+    blob = bytearray(make_plan(circ, B=2, projector=()).to_blob())
+    flags_off = 4 + 6 * 4
+    assert blob[flags_off] == 1
+    blob[flags_off] = 0
+    with pytest.raises(B.TnError):
+        B.tn_plan_validate(bytes(blob))
