@@ -195,6 +195,48 @@ def serve_bench(args):
     eng.close()
 
 
+def paper_families_bench(args):
+    """The paper's own circuit families at executable sizes, through the
+    planner and the executor: the IQP family (T = L^2 steps, gamma = 3) and
+    the Sycamore-type family (5 periods of 8 cycles, qubits inaccessible for
+    a period with probability 0.88, and 0.5 as a denser variant).  Reports
+    the counted cost of each plan (the paper's measure: real flops per
+    amplitude, Eq. (3)) beside the measured time."""
+    import numpy as np
+    from circuits import paper_iqp_circuit, sycamore_type_circuit, random_bitstrings
+    from paper_2208_01498_amd.planner.plan import make_plan
+    from paper_2208_01498_amd import binding as B
+    import torch
+    free, _ = torch.cuda.mem_get_info(0)
+    eng = B.Engine(0, arena_bytes=int(free - (8 << 30)))
+    prec = B.PRECISIONS[args.precision]
+    rows = []
+    for L in range(4, 9):
+        for fam, circ in (("iqp_T=L^2_gamma=3", paper_iqp_circuit(L, L * L, 5200 + L)),
+                          ("sycamore_type_q=5_p=0.88", sycamore_type_circuit(L, 5, 0.88, 5300 + L)),
+                          ("sycamore_type_q=5_p=0.5", sycamore_type_circuit(L, 5, 0.5, 5400 + L))):
+            words = random_bitstrings(circ.n, 64, 5500 + L)
+            t = time.perf_counter()
+            plan = make_plan(circ, n_slices=None, target_width=30, B=len(words))
+            t_plan = time.perf_counter() - t
+            h = eng.load(plan.to_blob())
+            eng.amplitudes(h, words, prec)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            eng.amplitudes(h, words, prec)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            rows.append({"family": fam, "L": L, "n": circ.n, "gates": len(circ.gates),
+                         "flops_per_amplitude": plan.stats["total_flops_per_b"],
+                         "max_rank": plan.stats["max_bits"], "slices": 1 << len(plan.sliced),
+                         "plan_s": t_plan, "amplitudes_per_s": len(words) / el})
+            log(json.dumps(rows[-1]))
+            B.tn_plan_unload(eng.ctx, h)
+    print(json.dumps({"metric": "paper families: counted flops and measured amplitudes/s",
+                      "precision": args.precision, "rows": rows, "data": "synthetic"}), flush=True)
+    eng.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +256,8 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="arrival rate as a fraction of the saturation rate")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--paper-families", action="store_true",
+                    help="the paper's IQP and Sycamore-type families at L = 4..8 instead")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a 1 GiB device copy, to scale the HBM byte counters")
     args = ap.parse_args()
@@ -226,6 +270,8 @@ def main():
         return serve_bench(args)
     if args.copy_calibration:
         return copy_calibration()
+    if args.paper_families:
+        return paper_families_bench(args)
 
     import numpy as np
     import torch

@@ -138,6 +138,41 @@ def paper_iqp_circuit(L, T, seed, gamma=3.0):
                    {"L": L, "T": T, "seed": seed, "gamma": gamma})
 
 
+def sycamore_type_circuit(L, periods, p_inaccessible, seed):
+    """The paper's second example on an L x L lattice: cycles of one
+    single-qubit gate per qubit (sqrt(X/Y/W), never the same twice in a row)
+    followed by fSim(pi/2, pi/6) on one of the four nearest-neighbour edge
+    patterns, eight cycles per period in the order A B C D C D A B (each
+    coupling applied twice per period), repeated for `periods` periods; in
+    each period every qubit is independently inaccessible with probability
+    `p_inaccessible`, and no gate acts on it during that period."""
+    rng = _rng(seed)
+    n = L * L
+    pats = edge_patterns(L, L)
+    order = [0, 1, 2, 3, 2, 3, 0, 1]
+    G2 = fsim(np.pi / 2, np.pi / 6)
+    gates = []
+    prev = [None] * n
+    for _ in range(periods):
+        off = rng.random(n) < p_inaccessible
+        for c in order:
+            for q in range(n):
+                if off[q]:
+                    continue
+                if prev[q] is None:
+                    k = int(rng.integers(len(SQRT_SET)))
+                else:
+                    choices = [i for i in range(len(SQRT_SET)) if i != prev[q]]
+                    k = choices[int(rng.integers(len(choices)))]
+                prev[q] = k
+                gates.append(Gate((q,), SQRT_SET[k][1].copy(), SQRT_SET[k][0]))
+            for (a, b) in pats[c]:
+                if not off[a] and not off[b]:
+                    gates.append(Gate((a, b), G2.copy(), "fSim"))
+    return Circuit(n, gates, lattice_positions(L, L), f"sycamoretype{L}x{L}_q{periods}",
+                   {"L": L, "periods": periods, "p": p_inaccessible, "seed": seed})
+
+
 def stack3d_circuit(X, Y, Z, layers, seed, name=""):
     """(2+1)-dimensional-style random circuit on an X x Y x Z qubit stack
     (q = x + X*y + X*Y*z).  Each layer picks an axis uniformly from {x,y,z}

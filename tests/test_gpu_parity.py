@@ -3,7 +3,8 @@ import numpy as np
 import pytest
 
 from circuits import (make_config, lattice_circuit, stack3d_circuit, iqp_lattice_circuit,
-                      random_bitstrings, mirror, product_circuit)
+                      random_bitstrings, mirror, product_circuit, paper_iqp_circuit,
+                      sycamore_type_circuit)
 from oracle import statevector_amplitudes, pairwise_amplitudes
 
 pytestmark = pytest.mark.gpu
@@ -56,6 +57,8 @@ FAMILIES = [
     ("stack_2x2x3", lambda: stack3d_circuit(2, 2, 3, 6, 204)),
     ("iqp_3x4", lambda: iqp_lattice_circuit(3, 4, 205)),
     ("product_8", lambda: product_circuit(8, 3, 206)),
+    ("paper_iqp_4x4_T16", lambda: paper_iqp_circuit(4, 16, 207)),
+    ("sycamore_type_4x4_p05", lambda: sycamore_type_circuit(4, 5, 0.5, 208)),
 ]
 
 

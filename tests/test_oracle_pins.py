@@ -8,7 +8,7 @@ import pytest
 
 from circuits import (lattice_circuit, iqp_lattice_circuit, stack3d_circuit,
                       product_circuit, mirror, random_bitstrings, make_config,
-                      paper_iqp_circuit, Circuit, Gate, haar_su2, haar_su4,
+                      paper_iqp_circuit, sycamore_type_circuit, Circuit, Gate, haar_su2, haar_su4,
                       SQRT_X, SQRT_Y, SQRT_W, H, CZ, fsim, cphase, z_phase)
 from circuits.families import serving_pool
 from oracle import (statevector, statevector_amplitudes, pairwise_amplitudes,
@@ -30,6 +30,7 @@ def _all_small_circuits():
         iqp_lattice_circuit(3, 3, 15),
         stack3d_circuit(2, 2, 3, 5, 16),
         paper_iqp_circuit(3, 4, 17),
+        sycamore_type_circuit(3, 2, 0.3, 18),
     ]
 
 
@@ -80,7 +81,7 @@ def test_two_qubit_index_convention_and_bit_order():
     assert np.max(np.abs(amps - want)) < 1e-15
 
 
-@pytest.mark.parametrize("idx", range(7))
+@pytest.mark.parametrize("idx", range(8))
 def test_statevector_equals_pairwise(idx):
     c = _all_small_circuits()[idx]
     words = random_bitstrings(c.n, 6, 100 + idx)
