@@ -231,7 +231,7 @@ def paper_families_bench(args):
                          "max_rank": plan.stats["max_bits"], "slices": 1 << len(plan.sliced),
                          "plan_s": t_plan, "amplitudes_per_s": len(words) / el})
             log(json.dumps(rows[-1]))
-            B.tn_plan_unload(eng.ctx, h)
+            eng.unload(h)
     print(json.dumps({"metric": "paper families: counted flops and measured amplitudes/s",
                       "precision": args.precision, "rows": rows, "data": "synthetic"}), flush=True)
     eng.close()
@@ -345,7 +345,8 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(circ, int(words[0]), seconds=args.cpu_seconds)
     out = {
-        "metric": "amplitudes/s, 8x8 depth-16 circuit (2^10 slices, 64 bitstrings)",
+        "metric": ("amplitudes/s, 8x8 depth-16 circuit (2^10 slices, 64 bitstrings)"
+                   if args.config == "cfg3" else "amplitudes/s, " + info["desc"]),
         "value": value, "unit": "amplitudes/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

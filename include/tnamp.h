@@ -118,7 +118,9 @@ int tn_plan_validate(const void* blob, size_t nbytes, tn_plan_info_t* info);
 
 int tn_plan_info(const tn_plan* plan, tn_plan_info_t* out);
 
-/* TN_EBUSY while requests on the plan are pending. */
+/* TN_EBUSY while requests on the plan are pending; TN_EINVAL for a plan that
+ * this context did not load or that was already unloaded.  tn_ctx_destroy
+ * unloads the plans still loaded. */
 int tn_plan_unload(tn_ctx* ctx, tn_plan* plan);
 
 /*

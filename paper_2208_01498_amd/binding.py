@@ -254,6 +254,10 @@ class Engine:
         self.plans.append(p)
         return p
 
+    def unload(self, plan):
+        tn_plan_unload(self.ctx, plan)
+        self.plans.remove(plan)
+
     def amplitudes(self, plan, words, precision=TN_FP32_4M):
         return tn_contract_amplitudes(self.ctx, plan, words, precision)
 
@@ -264,6 +268,7 @@ class Engine:
                     tn_plan_unload(self.ctx, p)
                 except TnError:
                     pass
+            self.plans = []
             tn_ctx_destroy(self.ctx)
             self.ctx = None
             self.arena = None

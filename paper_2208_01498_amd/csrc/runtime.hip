@@ -378,6 +378,11 @@ int tn_ctx_destroy(tn_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipStreamDestroy(ctx->stream);
     for (auto e : ctx->events) (void)hipEventDestroy(e);
+    for (tn_plan* p : ctx->plans) {      // plans still loaded
+        (void)hipFree(p->d_leaves);
+        delete p;
+    }
+    ctx->plans.clear();
     if (ctx->own_arena) (void)hipFree(ctx->arena);
     delete ctx;
     return TN_OK;
@@ -429,13 +434,22 @@ int tn_plan_load(tn_ctx* ctx, const void* blob, size_t nbytes, tn_plan** out) {
     }
     HIPCHK(ctx, hipMemcpy(pl->d_leaves, staging.data(), staging.size() * sizeof(float), hipMemcpyHostToDevice));
     pl->id = ctx->next_plan_id++;
+    {
+        std::lock_guard<std::mutex> g(ctx->smu);
+        ctx->plans.insert(pl.get());
+    }
     *out = pl.release();
     return TN_OK;
 }
 
 int tn_plan_unload(tn_ctx* ctx, tn_plan* plan) {
     if (!ctx || !plan) { set_error("null argument"); return TN_EINVAL; }
-    if (plan->pending.load() > 0) { set_error("plan has pending requests"); return TN_EBUSY; }
+    {
+        std::lock_guard<std::mutex> g(ctx->smu);
+        if (!ctx->plans.count(plan)) { set_error("plan is not loaded in this context"); return TN_EINVAL; }
+        if (plan->pending.load() > 0) { set_error("plan has pending requests"); return TN_EBUSY; }
+        ctx->plans.erase(plan);
+    }
     (void)hipSetDevice(ctx->device);
     (void)hipFree(plan->d_leaves);
     delete plan;

@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <deque>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -186,6 +187,7 @@ struct tn_ctx {
     // per-launch event timing (blocking calls only)
     bool profile = false;
     std::vector<hipEvent_t> events;
+    std::set<tn_plan*> plans;            // loaded and not yet unloaded (guarded by smu)
     int force_slice_block = -1;          // log2 slices per pass, -1 = automatic
 };
 

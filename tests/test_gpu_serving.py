@@ -157,3 +157,21 @@ def test_light_request_passes_a_waiting_heavy_batch():
             assert np.array_equal(got, want)
     finally:
         eng.close()
+
+
+def test_unload_twice_is_an_error():
+    """A plan unloaded once is no longer known to the context: a second
+    unload returns TN_EINVAL instead of touching freed memory, and
+    destroying the context afterwards is clean."""
+    from paper_2208_01498_amd import binding as B
+    circs, plans = _plans()
+    eng = B.Engine(0, arena_bytes=64 << 20)
+    try:
+        h = eng.load(plans[0].to_blob())
+        eng.load(plans[1].to_blob())          # left for the context to release
+        eng.unload(h)
+        with pytest.raises(B.TnError) as e:
+            B.tn_plan_unload(eng.ctx, h)
+        assert e.value.code == B.TN_EINVAL
+    finally:
+        eng.close()
