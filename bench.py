@@ -32,7 +32,8 @@ EXEC = {"fp32": 1.0, "fp32_3m": 0.75, "bf16x3": 3.0, "bf16x1": 1.0}
 # --no-cpu` (one chunk, the launch shapes of the default run), each scaled
 # by the counter's reading for a plain 1 GiB device
 # copy (`bench.py --copy-calibration`).  Keyed by the SHA-256 of the kernel's
-# source file: a changed kernel reports null until it is measured again.
+# source file, the plan's work per amplitude and the bitstring chunk: a
+# changed kernel or plan reports null until it is measured again.
 TRAFFIC = [
     {"class": "cgemm_mfma_128x128", "precision": "fp32_3m", "source": "gemm.hip",
      "source_sha256": "0ac99b6dd588fc8a0a0f79a04cb87066cc3bfac954735e2e6dd5751fe3c2381a",
@@ -337,8 +338,12 @@ def main():
                "peak": 8000.0, "unit": "GB/s", "launches": prof["launches"][4], "ms": pm}
     permute["frac"] = permute["achieved"] / permute["peak"]
     for rec in TRAFFIC:
+        # the same kernel source, precision and launches (the plan's work per
+        # amplitude and the bitstring chunk fix the launch shapes)
         if (rec["class"] == kinds[dom] and rec["precision"] == args.precision and
-                rec["source_sha256"] == source_hash(rec["source"])):
+                rec["source_sha256"] == source_hash(rec["source"]) and
+                rec.get("chunk") == st["chunk"] and
+                abs(rec.get("flops_per_amplitude", 0) / (st["algorithmic_flops"] / nb) - 1) < 1e-6):
             roofline["traffic"] = rec["bytes_per_launch"]
             roofline["traffic_note"] = rec["note"]
     cpu = None

@@ -28,6 +28,7 @@ import numpy as np
 
 from .network import build_network
 from .hierarchy import TreeBuilder, tree_steps
+from .toporder import refine_top
 from .slicer import SliceModel
 from .layout import Layout
 from .cost import plan_stats
@@ -103,12 +104,15 @@ class Plan:
 
 
 def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
-              n_circles=24, trials=1, objective="time", coarsen=0, projector=None):
+              n_circles=24, trials=1, objective="time", coarsen=0, projector=None,
+              top_exact=13):
     """Build a plan.  ``n_slices``: number of sliced labels (log2 of the slice
     count), or None to slice until the widest per-slice intermediate is at
     most ``target_width`` (log2 elements, batch included).  ``projector``:
     None for amplitudes <x|C|0>; otherwise the set of traced qubits of the
-    projector quantity <0|C^dag (x)_q P_q C|0> (P_q = |x_q><x_q| elsewhere)."""
+    projector quantity <0|C^dag (x)_q P_q C|0> (P_q = |x_q><x_q| elsewhere).
+    ``top_exact``: size of the frontier below the root whose pairwise order
+    is chosen exactly (0 keeps the hierarchy's order everywhere)."""
     from .network import _is_swap_diag, build_doubled_network
     forms = [False]
     if projector is None and any(len(g.qubits) == 2 and _is_swap_diag(g.matrix) for g in circ.gates):
@@ -123,6 +127,8 @@ def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
             tb = TreeBuilder(net, np.random.Generator(np.random.PCG64(seed + t)),
                              bottom=bottom, n_circles=n_circles)
             root = tb.build()
+            if top_exact:
+                root = refine_top(root, tb, B=B, frontier=top_exact)
             steps = tree_steps(root, len(net.factors))
             st = plan_stats(net, steps, B=1)
             if best is None or st["flops"] < best[0]:

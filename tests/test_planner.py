@@ -273,3 +273,23 @@ def test_projector_blob_accepted_and_amplitude_blob_rules_kept():
     blob[flags_off] = 0
     with pytest.raises(B.TnError):
         B.tn_plan_validate(bytes(blob))
+
+
+@pytest.mark.parametrize("name,mk", CIRCS[:4], ids=[c[0] for c in CIRCS[:4]])
+def test_exact_top_order_never_costs_more(name, mk):
+    """The exact order of the top frontier is chosen among all pairwise
+    orders of the frontier, which include the hierarchy's own order: the
+    refined tree never costs more (Eq. (3) count), and the refined plan is
+    still the same contraction (oracle-evaluated order equals the state
+    vector)."""
+    circ = mk()
+    # B = 1: the exact order minimises the same count that plan_stats reports
+    base = make_plan(circ, B=1, top_exact=0)
+    ref = make_plan(circ, B=1, top_exact=10)
+    fb = plan_stats(base.net, base.steps, B=1)["flops"]
+    fr = plan_stats(ref.net, ref.steps, B=1)["flops"]
+    assert fr <= fb * (1 + 1e-12)
+    words = random_bitstrings(circ.n, 3, 470)
+    spec = ref.order_spec()
+    got = pairwise_amplitudes(circ, words, order=spec, sliced=spec["sliced"])
+    assert np.max(np.abs(got - statevector_amplitudes(circ, words))) <= 1e-12
