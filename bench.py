@@ -28,19 +28,20 @@ PEAK = {"fp32": 157.3e12, "fp32_3m": 157.3e12, "bf16x3": 2516.6e12, "bf16x1": 25
 EXEC = {"fp32": 1.0, "fp32_3m": 0.75, "bf16x3": 3.0, "bf16x1": 1.0}
 
 # HBM traffic per launch of a kernel class, from two rocprofv3 --pmc passes
-# (FETCH_SIZE, WRITE_SIZE) over `bench.py --batch 6 --warmup 0 --steps 1
-# --no-cpu` (one chunk, the launch shapes of the default run), each scaled
-# by the counter's reading for a plain 1 GiB device
+# (FETCH_SIZE, WRITE_SIZE) over `bench.py --warmup 0 --steps 1 --no-cpu`
+# (the launches of one timed step), each scaled by the counter's reading
+# for a plain 1 GiB device
 # copy (`bench.py --copy-calibration`).  Keyed by the SHA-256 of the kernel's
 # source file, the plan's work per amplitude and the bitstring chunk: a
 # changed kernel or plan reports null until it is measured again.
 TRAFFIC = [
     {"class": "cgemm_mfma_128x128", "precision": "fp32_3m", "source": "gemm.hip",
      "source_sha256": "0ac99b6dd588fc8a0a0f79a04cb87066cc3bfac954735e2e6dd5751fe3c2381a",
-     "bytes_per_launch": 1.191e11,
-     "note": "HBM fetch 9.721e10 + write 2.188e10 bytes per launch (48 launches of a chunk of 6 "
-             "bitstrings; FETCH_SIZE x2.0 and WRITE_SIZE x1.0 from a 1 GiB copy); algorithmic "
-             "3.741e10"},
+     "chunk": 26, "flops_per_amplitude": 40288685565267.0,
+     "bytes_per_launch": 1.736e11,
+     "note": "HBM fetch 1.592e11 + write 1.438e10 bytes per launch (the 141 launches of one "
+             "timed step; FETCH_SIZE x2.0 and WRITE_SIZE x1.0 from a 1 GiB copy); algorithmic "
+             "1.847e10"},
 ]
 
 
