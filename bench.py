@@ -5,7 +5,7 @@ dominant GEMM kernel and the CPU oracle timed beside it.
 One step = one tn_contract_amplitudes call over the whole batch (all slices,
 all chunks), inputs resident: the plan is built and loaded before timing.
 
-  python bench.py [--steps K] [--warmup W] [--precision fp32_3m|fp32|bf16x3]
+  python bench.py [--steps K] [--warmup W] [--precision fp32_3m|fp32|bf16x3|fp16x3]
                   [--config cfg3] [--batch B] [--slices S] [--width W]
                   [--no-cpu]
 
@@ -21,11 +21,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32": 157.3e12, "fp32_3m": 157.3e12, "bf16x3": 2516.6e12, "bf16x1": 2516.6e12}
+PEAK = {"fp32": 157.3e12, "fp32_3m": 157.3e12, "bf16x3": 2516.6e12, "fp16x3": 2516.6e12,
+        "bf16x1": 2516.6e12}
 # executed MFMA flops per algorithmic flop (8 real flops per complex
 # multiply-add): 4M executes exactly those, 3M three real products instead
-# of four, split bf16 three 16-bit products of the 4M form
-EXEC = {"fp32": 1.0, "fp32_3m": 0.75, "bf16x3": 3.0, "bf16x1": 1.0}
+# of four, split bf16 and fp16 three 16-bit products of the 4M form
+EXEC = {"fp32": 1.0, "fp32_3m": 0.75, "bf16x3": 3.0, "fp16x3": 3.0, "bf16x1": 1.0}
 
 # HBM traffic per launch of a kernel class, from two rocprofv3 --pmc passes
 # (FETCH_SIZE, WRITE_SIZE) over `bench.py --warmup 0 --steps 1 --no-cpu`
@@ -245,7 +246,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="cfg3")
-    ap.add_argument("--precision", default="fp32_3m", choices=["fp32", "fp32_3m", "bf16x3", "bf16x1"])
+    ap.add_argument("--precision", default="fp32_3m", choices=["fp32", "fp32_3m", "bf16x3", "fp16x3", "bf16x1"])
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--slices", type=int, default=10)
     ap.add_argument("--width", type=float, default=None)
@@ -357,7 +358,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp32": "c64/f32-mfma", "fp32_3m": "c64/f32-mfma-3m",
-                  "bf16x3": "bf16x3-mfma/f32-acc", "bf16x1": "bf16-mfma/f32-acc"}[args.precision],
+                  "bf16x3": "bf16x3-mfma/f32-acc", "fp16x3": "fp16x3-mfma/f32-acc",
+                  "bf16x1": "bf16-mfma/f32-acc"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (args.config, info["desc"]), "batch": nb,
                    "slices": 1 << len(plan.sliced), "precision": args.precision,

@@ -52,8 +52,13 @@ extern "C" {
                                Ar Br, Ai Bi, (Ar+Ai)(Br+Bi); steps whose output
                                has at most 16 entries use the 4M dot kernel */
 #define TN_SPLIT_BF16 2     /* x = hi + lo in bf16, hi*hi + hi*lo + lo*hi, FP32 acc */
-#define TN_SPLIT_FP16 3     /* reserved: fp16 halves with power-of-two scaling;
-                               rejected with TN_EINVAL */
+#define TN_SPLIT_FP16 3     /* x = hi + lo in fp16 after a power-of-two scale per
+                               row of A and column of B (largest |re|, |im|
+                               scaled into [2^14, 2^15)), hi*hi + hi*lo + lo*hi,
+                               FP32 acc, both scales undone exactly in the
+                               epilogue; the scales depend only on that row's
+                               (column's) own entries, so a result does not
+                               depend on the chunk or co-scheduled requests */
 #define TN_BF16_1TERM 4     /* operands rounded once to bf16, one product per
                                complex product, FP32 accumulation: the plain
                                rounding reference point for the split mode */
@@ -217,9 +222,9 @@ int tn_last_exec_stats(tn_ctx* ctx, tn_exec_stats* out);
  *   A(m,k) = A[ob*sAb + ib*sAi + (transA ? k*M + m : m*K + k)]
  *   B(k,n) = B[ob*sBb + ib*sBi + (transB ? n*K + k : k*N + n)]
  *   strides in complex elements; sAb or sBb may be 0 (broadcast); M, N, K
- *   powers of two.  precision TN_FP32_4M, TN_FP32_3M, TN_SPLIT_BF16 or
- *   TN_BF16_1TERM.  `scratch`:
- *   device memory for split-K partial sums (see
+ *   powers of two.  precision TN_FP32_4M, TN_FP32_3M, TN_SPLIT_BF16,
+ *   TN_SPLIT_FP16 or TN_BF16_1TERM.  `scratch`: device memory for split-K
+ *   partial sums and, for TN_SPLIT_FP16, the row and column maxima (see
  *   tn_kernel_cgemm_scratch_bytes).  Returns TN_EINVAL for bad sizes or too
  *   little scratch, TN_EDEVICE on a launch error.
  * tn_kernel_permute: bit permutation of the element index:
@@ -232,8 +237,10 @@ int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N,
                     int64_t sAb, int64_t sBb, int64_t sCb, int64_t sAi, int64_t sBi,
                     int64_t sCi, int32_t precision, void* scratch, size_t scratch_bytes,
                     void* hip_stream);
-/* Device scratch tn_kernel_cgemm needs for this shape (0 when the shape runs
- * without a K split); a call with less returns TN_EINVAL. */
+/* Device scratch tn_kernel_cgemm needs for this shape in any precision mode
+ * (split-K partials, 256-byte aligned, then 4 bytes per row of A and column
+ * of B for TN_SPLIT_FP16); a call with less than its mode needs returns
+ * TN_EINVAL. */
 size_t tn_kernel_cgemm_scratch_bytes(int32_t M, int32_t N, int32_t K, int32_t nbatch, int32_t nb);
 int tn_kernel_permute(const void* src, void* dst, int32_t rank, const int32_t* perm,
                       int32_t nb, void* hip_stream);

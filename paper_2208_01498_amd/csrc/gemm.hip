@@ -12,6 +12,11 @@
 //                   split x = hi + lo when staged into LDS, and
 //                   hi*hi + hi*lo + lo*hi are accumulated in FP32; one MFMA is
 //                   32 x 16 x 8 (complex)
+//   k_cgemm<3,...>  split fp16 on v_mfma_f32_32x32x16_f16: every row of A
+//                   and column of B is first scaled by a power of two that
+//                   puts its largest |re|, |im| in [2^14, 2^15) (k_opmax
+//                   finds the maxima), then split into fp16 hi + lo as
+//                   above; the epilogue undoes both scales exactly
 //   k_cgemm<4,...>  the same with hi*hi only (plain bf16 rounding of the
 //                   operands), kept as the lower-accuracy reference point
 //   k_cgemm3m       FP32 3M on the same MFMA used as a real 32 x 32 x 2
@@ -37,6 +42,7 @@
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
@@ -51,6 +57,19 @@ __device__ __forceinline__ size_t pext_u(size_t x, unsigned m) {
     for (; m; m &= m - 1, ++k)
         if (x & (m & (~m + 1))) r |= size_t(1) << k;
     return r;
+}
+
+// Operand copy read by the GEMM block of outer bitstring bb, inner batch ib
+// and slice-block copy rr, numbered over the copies that exist: bitstrings
+// only when the operand has them (stride != 0), slice-block copies only when
+// they form an outer batch (fold 0).  Indexes the row (column) maxima of the
+// split fp16 products, so each copy's maxima are found once.
+__device__ __forceinline__ size_t operand_copy(const GemmArgs& g, int op, size_t bb, size_t ib, size_t rr) {
+    const long long sb = op ? g.sBb : g.sAb;
+    const unsigned m = op ? g.mB : g.mA;
+    const size_t nc = g.fold == 0 ? (size_t(1) << __builtin_popcount(m)) : 1;
+    const size_t c = g.fold == 0 ? pext_u(rr, m) : 0;
+    return ((sb ? bb : 0) * g.nbatch + ib) * nc + c;
 }
 
 // Row deposits for a 32-row MFMA output block under a scattered C: row
@@ -77,6 +96,24 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
     hi = __float2bfloat16(x);
     lo = __float2bfloat16(x - __bfloat162float(hi));
 }
+
+// fp16 halves of a value already scaled into the fp16 range: x - hi is
+// exact in FP32, and both conversions round to nearest even
+__device__ __forceinline__ void split_f16(float x, _Float16& hi, _Float16& lo) {
+    hi = (_Float16)x;
+    lo = (_Float16)(x - (float)hi);
+}
+
+// Power-of-two scale 2^t for a row whose largest |re|, |im| has the float
+// bit pattern `mx` (2^e <= max < 2^(e+1)): t = 14 - e puts the scaled
+// maximum in [2^14, 2^15), below the fp16 limit of 65504; t is clamped so
+// that 2^t and 2^-t are normal floats; an all-zero row keeps scale 1
+__device__ __forceinline__ int scale_exp(unsigned mx) {
+    if (mx == 0) return 0;
+    const int e = (int)((mx >> 23) & 255u) - 127;
+    return min(126, max(-126, 14 - e));
+}
+__device__ __forceinline__ float exp2i(int t) { return __uint_as_float((unsigned)(127 + t) << 23); }
 
 template <int PREC, int WGM, int WGN, int WMF, int WNF>
 struct Smem {
@@ -155,6 +192,29 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
     float4 ra[LA], rb[LB];
+    // split fp16: scales of the rows (A) and columns (B) this thread stages;
+    // element 0 of a staged pair at index 0, element 1 at index 1
+    float sca[LA][2], scb[LB][2];
+    if constexpr (PREC == 3) {
+        const unsigned* xa = g.xA + operand_copy(g, 0, bb, ib, rr) * Mt;
+        const unsigned* xb = g.xB + operand_copy(g, 1, bb, ib, rr) * Nt;
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            const int f = tid + i * NT;
+            const int m = !TA ? f / (KT / 2) : 2 * (f % (BM / 2));
+            const int m2 = !TA ? m : m + 1;
+            sca[i][0] = (f < FA && m0 + m < Mt) ? exp2i(scale_exp(xa[m0 + m])) : 1.f;
+            sca[i][1] = (f < FA && m0 + m2 < Mt) ? exp2i(scale_exp(xa[m0 + m2])) : 1.f;
+        }
+#pragma unroll
+        for (int i = 0; i < LB; ++i) {
+            const int f = tid + i * NT;
+            const int n = !TB ? 2 * (f % (BN / 2)) : f / (KT / 2);
+            const int n2 = !TB ? n + 1 : n;
+            scb[i][0] = (f < FB && n0 + n < Nt) ? exp2i(scale_exp(xb[n0 + n])) : 1.f;
+            scb[i][1] = (f < FB && n0 + n2 < Nt) ? exp2i(scale_exp(xb[n0 + n2])) : 1.f;
+        }
+    }
     // address of A(m', k) / B(k, n') for folded indices
     auto adA = [&](int mp, int k) -> size_t {
         const int m = mp & (g.M - 1);
@@ -227,13 +287,27 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
     __bf16* Bh = Al + 2 * BM * RA;                               // [2][2BN][RA]
     __bf16* Bl = Bh + 2 * 2 * BN * RA;
 
-    // two floats -> packed bf16 pairs (hi, lo) with x = hi + lo
-    auto split2 = [](float a, float b, uint32_t& hi, uint32_t& lo) {
-        __bf16 ha, la, hb, lb;
-        split_bf16(a, ha, la);
-        split_bf16(b, hb, lb);
-        hi = (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
-        lo = (uint32_t)__builtin_bit_cast(uint16_t, la) | ((uint32_t)__builtin_bit_cast(uint16_t, lb) << 16);
+    // two floats (one complex, both times the scale sc of its row or
+    // column in fp16 mode) -> packed 16-bit pairs (hi, lo), x = hi + lo; the
+    // 16-bit planes hold bf16 or fp16 bit patterns
+    auto split2 = [](float a, float b, float sc, uint32_t& hi, uint32_t& lo) {
+        uint16_t h0, l0, h1, l1;
+        if constexpr (PREC == 3) {
+            _Float16 ha, la, hb, lb;
+            split_f16(a * sc, ha, la);
+            split_f16(b * sc, hb, lb);
+            h0 = __builtin_bit_cast(uint16_t, ha); l0 = __builtin_bit_cast(uint16_t, la);
+            h1 = __builtin_bit_cast(uint16_t, hb); l1 = __builtin_bit_cast(uint16_t, lb);
+        } else {
+            (void)sc;
+            __bf16 ha, la, hb, lb;
+            split_bf16(a, ha, la);
+            split_bf16(b, hb, lb);
+            h0 = __builtin_bit_cast(uint16_t, ha); l0 = __builtin_bit_cast(uint16_t, la);
+            h1 = __builtin_bit_cast(uint16_t, hb); l1 = __builtin_bit_cast(uint16_t, lb);
+        }
+        hi = (uint32_t)h0 | ((uint32_t)h1 << 16);
+        lo = (uint32_t)l0 | ((uint32_t)l1 << 16);
     };
 
     auto store = [&](int buf) {
@@ -255,8 +329,8 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
                 uint32_t* ah = reinterpret_cast<uint32_t*>(Ah + buf * BM * RA);
                 uint32_t* al = reinterpret_cast<uint32_t*>(Al + buf * BM * RA);
                 uint32_t h0, l0, h1, l1;
-                split2(ra[i].x, ra[i].y, h0, l0);
-                split2(ra[i].z, ra[i].w, h1, l1);
+                split2(ra[i].x, ra[i].y, sca[i][0], h0, l0);
+                split2(ra[i].z, ra[i].w, sca[i][1], h1, l1);
                 // real index 2k + (re, im) of row m: one 4-byte word per complex
                 ah[(m * RA + 2 * k) / 2] = h0; al[(m * RA + 2 * k) / 2] = l0;
                 ah[(m2 * RA + 2 * k2) / 2] = h1; al[(m2 * RA + 2 * k2) / 2] = l1;
@@ -280,8 +354,8 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
                 // (Bi, Br).  Each real is split once; the negated halves of
                 // -Bi are the halves of Bi with the sign bit flipped (exact)
                 uint32_t h0, l0, h1, l1;
-                split2(rb[i].x, rb[i].y, h0, l0);       // (Br, Bi) of element 0
-                split2(rb[i].z, rb[i].w, h1, l1);       // element 1
+                split2(rb[i].x, rb[i].y, scb[i][0], h0, l0);   // (Br, Bi) of element 0
+                split2(rb[i].z, rb[i].w, scb[i][1], h1, l1);   // element 1
                 auto neg_hi = [](uint32_t v) {           // (r, i) -> (r, -i)
                     return v ^ 0x80000000u;
                 };
@@ -348,11 +422,20 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
                 for (int i = 0; i < WMF; ++i)
 #pragma unroll
                     for (int j = 0; j < WNF; ++j) {
-                        if constexpr (PREC == 2) {
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], yh[j], acc[i][j], 0, 0, 0);
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yl[j], acc[i][j], 0, 0, 0);
+                        if constexpr (PREC == 3) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                                __builtin_bit_cast(halfx8, xl[i]), __builtin_bit_cast(halfx8, yh[j]), acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                                __builtin_bit_cast(halfx8, xh[i]), __builtin_bit_cast(halfx8, yl[j]), acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                                __builtin_bit_cast(halfx8, xh[i]), __builtin_bit_cast(halfx8, yh[j]), acc[i][j], 0, 0, 0);
+                        } else {
+                            if constexpr (PREC == 2) {
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], yh[j], acc[i][j], 0, 0, 0);
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yl[j], acc[i][j], 0, 0, 0);
+                            }
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yh[j], acc[i][j], 0, 0, 0);
                         }
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yh[j], acc[i][j], 0, 0, 0);
                     }
             }
         }
@@ -387,6 +470,11 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
             unsigned long long dbase = 0;
             if (fastdep)
                 dbase = pdep64((unsigned)((m0 + wm + i * 32) & (g.M - 1)), g.cPM) | pdep64((unsigned)n, g.cPN);
+            // split fp16: undo the column scale, then the row scale (exact
+            // multiplications by powers of two)
+            float ucol = 1.f;
+            if constexpr (PREC == 3)
+                ucol = exp2i(-scale_exp(g.xB[operand_copy(g, 1, bb, ib, rr) * Nt + np]));
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int mp = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
@@ -398,7 +486,10 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
                     e = (size_t)gemm_c_copy(g, (unsigned)(mp >> lgM), (unsigned)(np >> lgN)) +
                         (fastdep ? (size_t)(dbase | rd.low(r, half)) : gemm_c_elem(g, m, n));
                 }
-                reinterpret_cast<float*>(Cb + e)[l32 & 1] = acc[i][j][r];
+                float v = acc[i][j][r];
+                if constexpr (PREC == 3)
+                    v = (v * ucol) * exp2i(-scale_exp(g.xA[operand_copy(g, 0, bb, ib, rr) * Mt + mp]));
+                reinterpret_cast<float*>(Cb + e)[l32 & 1] = v;
             }
         }
 }
@@ -763,6 +854,91 @@ __global__ void k_reduce_splitk(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// Largest |re|, |im| over k of every row of A (OP = 0) or column of B
+// (OP = 1), for every operand copy the GEMM reads, as the float's bit
+// pattern (non-negative floats order like their bits): out[copy * R + row],
+// copy as numbered by operand_copy, R = folded rows (columns).  CONTIG:
+// k is the contiguous index, so L = min(K, 64) consecutive lanes read
+// consecutive k of one row and combine by shuffles; otherwise consecutive
+// lanes take consecutive rows at the same k.  Each thread covers OPMAX_KS
+// values of k; the partial maxima meet by atomicMax (the words start at 0).
+constexpr int OPMAX_KS = 32;
+
+__global__ void k_zero_words(unsigned* p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+template <int OP, bool CONTIG>
+__global__ void __launch_bounds__(256) k_opmax(GemmArgs g, unsigned* out, size_t total) {
+    const int R = OP == 0 ? gemm_rows(g) : gemm_cols(g);
+    const int lgX = __builtin_ctz((unsigned)(OP == 0 ? g.M : g.N));
+    const int X = OP == 0 ? g.M : g.N;
+    const int K = g.K;
+    const int L = K < 64 ? K : 64;                  // CONTIG lanes per row
+    const size_t per = (size_t)(CONTIG ? L : 1) * OPMAX_KS;
+    const size_t kchunks = (K + per - 1) / per;
+    const size_t items = total * kchunks * (CONTIG ? L : 1);
+    // grid-stride over work items; the bound is rounded up to whole
+    // workgroups so that every lane of a wave runs the same number of
+    // rounds (the shuffles below need the whole wave)
+    const size_t bound = (items + 255) / 256 * 256;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < bound; t += stride) {
+        size_t row_all, kc;
+        int lane_k;
+        if (CONTIG) {
+            lane_k = (int)(t % L);
+            const size_t grp = t / L;
+            kc = grp % kchunks;
+            row_all = grp / kchunks;
+        } else {
+            lane_k = 0;
+            row_all = t % total;
+            kc = t / total;
+        }
+        float mx = 0.f;
+        const bool live = t < items;
+        if (live) {
+            // operand copy (numbered as operand_copy does) and row within it
+            const size_t inst = row_all / R;
+            const int row = (int)(row_all % R);
+            const unsigned m = OP ? g.mB : g.mA;
+            const size_t nc = g.fold == 0 ? (size_t(1) << __builtin_popcount(m)) : 1;
+            const size_t c = inst % nc;
+            const size_t ib = (inst / nc) % g.nbatch, bx = inst / nc / g.nbatch;
+            const float2* base;
+            long long sF;
+            bool trans;
+            if (OP == 0) {
+                base = g.A + bx * g.sAb + ib * g.sAi + c * g.sAr;
+                sF = (g.fold == 2 || g.fold == 3) ? g.sAr : 0;
+                trans = g.transA;
+            } else {
+                base = g.B + bx * g.sBb + ib * g.sBi + c * g.sBr;
+                sF = (g.fold == 1 || g.fold == 3) ? g.sBr : 0;
+                trans = !g.transB;       // B stored [k][n]: k is not contiguous
+            }
+            const int x = row & (X - 1);
+            const float2* p = base + (size_t)(row >> lgX) * sF;
+            const int kb = (int)(kc * per);
+            for (int s = 0; s < OPMAX_KS; ++s) {
+                const int k = CONTIG ? kb + s * L + lane_k : kb + s;
+                if (k >= K) break;
+                const float2 v = trans ? p[(size_t)k * X + x] : p[(size_t)x * K + k];
+                mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+            }
+        }
+        if (CONTIG) {
+            for (int o = 1; o < L; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+            if (live && lane_k == 0) atomicMax(out + row_all, __float_as_uint(mx));
+        } else if (live) {
+            atomicMax(out + row_all, __float_as_uint(mx));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host-side dispatch
 
 static int ilog2(long long x) { int r = 0; while ((1ll << r) < x) ++r; return r; }
@@ -808,6 +984,12 @@ size_t gemm_scratch_elems(int M, int N, int K, int nbatch, int nouter) {
     GemmChoice c = choose_gemm(M, N, K, nbatch);
     if (c.splits <= 1) return 0;
     return (size_t)c.splits * nouter * nbatch * (size_t)M * N;
+}
+
+size_t gemm_scale_words(int M, int N, int K, int nbatch, int nouter) {
+    GemmChoice c = choose_gemm(M, N, K, nbatch);
+    if (c.kind == GEMM_DOT) return 0;
+    return (size_t)nouter * nbatch * ((size_t)M + N);
 }
 
 template <int PREC, int WGM, int WGN, int WMF, int WNF, bool TA, bool TB>
@@ -862,6 +1044,7 @@ static void launch_cfg3(const GemmArgs& g, size_t grid, hipStream_t s) {
 template <int WGM, int WGN, int WMF, int WNF>
 static void launch_prec(const GemmArgs& g, int precision, size_t grid, hipStream_t s) {
     if (precision == 2) launch_cfg<2, WGM, WGN, WMF, WNF>(g, grid, s);
+    else if (precision == 3) launch_cfg<3, WGM, WGN, WMF, WNF>(g, grid, s);
     else if (precision == 4) launch_cfg<4, WGM, WGN, WMF, WNF>(g, grid, s);
     else launch_cfg<0, WGM, WGN, WMF, WNF>(g, grid, s);
 }
@@ -907,6 +1090,37 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
             else hipLaunchKernelGGL((k_cgemm_dot<false, false>), dim3((unsigned)batches), dim3(256), 0, s, g);
         }
     } else {
+        if (precision == 3) {
+            // row maxima of A, column maxima of B over every operand copy
+            if (!g.X) return hipErrorInvalidValue;
+            // one set of maxima per operand copy (see operand_copy)
+            auto copies = [&](long long sb, unsigned m) -> size_t {
+                return (sb ? (size_t)g.nb : 1) * g.nbatch * (g.fold == 0 ? (size_t(1) << __builtin_popcount(m)) : 1);
+            };
+            const size_t ra = (size_t)Mt * copies(g.sAb, g.mA), rb = (size_t)Nt * copies(g.sBb, g.mB);
+            unsigned* xa = g.X;
+            unsigned* xb = g.X + ra;
+            g.xA = xa;
+            g.xB = xb;
+            const unsigned zb = (unsigned)std::min<size_t>((ra + rb + 255) / 256, 1u << 16);
+            hipLaunchKernelGGL(k_zero_words, dim3(zb), dim3(256), 0, s, xa, ra + rb);
+            const int L = std::min(g.K, 64);
+            for (int op = 0; op < 2; ++op) {
+                const size_t rows = op ? rb : ra;
+                const bool contig = op ? g.transB : !g.transA;
+                const size_t per = contig ? (size_t)L * OPMAX_KS : (size_t)OPMAX_KS;
+                const size_t items = rows * ((g.K + per - 1) / per) * (contig ? L : 1);
+                const size_t blocks = std::min<size_t>((items + 255) / 256, 1u << 16);
+                unsigned* out = op ? xb : xa;
+                if (op == 0) {
+                    if (contig) hipLaunchKernelGGL((k_opmax<0, true>), dim3((unsigned)blocks), dim3(256), 0, s, g, out, rows);
+                    else hipLaunchKernelGGL((k_opmax<0, false>), dim3((unsigned)blocks), dim3(256), 0, s, g, out, rows);
+                } else {
+                    if (contig) hipLaunchKernelGGL((k_opmax<1, true>), dim3((unsigned)blocks), dim3(256), 0, s, g, out, rows);
+                    else hipLaunchKernelGGL((k_opmax<1, false>), dim3((unsigned)blocks), dim3(256), 0, s, g, out, rows);
+                }
+            }
+        }
         int bm = 128, bn = 128;
         if (c.kind == GEMM_MFMA_128x128 && precision == 1) bn = 64;
         if (c.kind == GEMM_MFMA_64x64) { bm = 64; bn = 64; }

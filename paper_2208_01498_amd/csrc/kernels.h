@@ -60,6 +60,11 @@ struct GemmArgs {
     long long sAr, sBr, sCr;  // slice-block strides; 0 = broadcast
     int scatter;              // C element (m, n) at pdep(m, cPM) | pdep(n, cPN)
     unsigned long long cPM, cPN;
+    unsigned* X;              // split fp16 only: workspace for the largest |re|, |im|
+                              // of every row of A and column of B (float bits),
+                              // gemm_scale_words() words
+    const unsigned* xA;       // set by the dispatcher: [outer][inner batch][m']
+    const unsigned* xB;       // [outer][inner batch][n']
 };
 
 // Folded GEMM sizes: the row index m' = a * M + m and column index
@@ -108,6 +113,10 @@ struct GemmChoice {
 // not change any element's summation order.
 GemmChoice choose_gemm(int M, int N, int K, int nbatch, int Mt = 0, int Nt = 0);
 size_t gemm_scratch_elems(int M, int N, int K, int nbatch, int nouter);
+// 32-bit words of row and column maxima the split fp16 products need (0 for
+// shapes that take the dot-product kernel); nouter counts bitstrings times
+// slice-block copies of C
+size_t gemm_scale_words(int M, int N, int K, int nbatch, int nouter);
 hipError_t launch_gemm(const GemmArgs& g, int precision, hipStream_t s);
 int gemm_kind(const GemmArgs& g, int precision);
 hipError_t launch_zero_acc(double2* acc, int nb, hipStream_t s);

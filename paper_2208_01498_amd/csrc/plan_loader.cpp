@@ -373,10 +373,11 @@ int parse_plan(const void* blob, size_t nbytes, PlanHost& p) {
 // loop; all others live from their producing step to their consuming step.
 // Buffers are placed first-fit by decreasing size, never overlapping a
 // buffer whose lifetime overlaps.
-MemPlan plan_memory(const PlanHost& p, int chunk, int r) {
+MemPlan plan_memory(const PlanHost& p, int chunk, int r, bool scales) {
     MemPlan mp;
     mp.chunk = chunk;
     mp.r = r;
+    mp.scales = scales;
     const uint32_t low = (1u << r) - 1;
     const int nL = (int)p.leaves.size();
     const int T = (int)p.rank.size();
@@ -386,6 +387,7 @@ MemPlan plan_memory(const PlanHost& p, int chunk, int r) {
     mp.permA_off.assign(p.steps.size(), kNone);
     mp.permB_off.assign(p.steps.size(), kNone);
     mp.scratch_off.assign(p.steps.size(), kNone);
+    mp.scale_off.assign(p.steps.size(), kNone);
     struct Buf { size_t bytes; int start, end; size_t* off; };
     std::vector<Buf> bufs;
     // a tensor whose subtree holds low slice bits exists once per slice of the
@@ -440,6 +442,10 @@ MemPlan plan_memory(const PlanHost& p, int chunk, int r) {
         const int nouter = (st.hbC ? chunk : 1) * (1 << __builtin_popcount(st.dep_mask & low));
         size_t se = gemm_scratch_elems(Mk, Nk, K, 1 << st.batch_bits, nouter);
         if (se) bufs.push_back({se * 8, (int)s, (int)s, &mp.scratch_off[s]});
+        if (scales) {
+            size_t sw = gemm_scale_words(Mk, Nk, K, 1 << st.batch_bits, nouter);
+            if (sw) bufs.push_back({sw * 4, (int)s, (int)s, &mp.scale_off[s]});
+        }
     }
     for (auto& b : bufs) b.bytes = (b.bytes + 255) / 256 * 256;
     std::vector<int> idx(bufs.size());
@@ -469,11 +475,11 @@ MemPlan plan_memory(const PlanHost& p, int chunk, int r) {
 
 }  // namespace tn
 
-const tn::MemPlan& tn_plan::mem(int chunk, int r) {
+const tn::MemPlan& tn_plan::mem(int chunk, int r, bool scales) {
     std::lock_guard<std::mutex> g(mcache);
-    const long long key = (long long)chunk * 64 + r;
+    const long long key = ((long long)chunk * 64 + r) * 2 + (scales ? 1 : 0);
     auto it = memcache.find(key);
     if (it != memcache.end()) return it->second;
-    auto& v = memcache[key] = tn::plan_memory(host, chunk, r);
+    auto& v = memcache[key] = tn::plan_memory(host, chunk, r, scales);
     return v;
 }

@@ -80,18 +80,18 @@ static void fill_perm(PermArgs& pa, const int* map, int r) {
 // largest block that fits with at least one bitstring is taken (a forced r
 // from the context option wins when it fits), then the largest chunk.
 bool choose_shape(const tn_plan* plan, int nb, size_t ws_bytes, int force_r, int& r_out,
-                         int& chunk_out) {
+                  int& chunk_out, bool scales) {
     tn_plan* pl = const_cast<tn_plan*>(plan);
     const int S = (int)plan->host.sliced.size();
     int r = -1;
-    if (force_r >= 0 && force_r <= S && pl->mem(1, force_r).bytes <= ws_bytes) r = force_r;
+    if (force_r >= 0 && force_r <= S && pl->mem(1, force_r, scales).bytes <= ws_bytes) r = force_r;
     for (int rr = S; r < 0 && rr >= 0; --rr)
-        if (pl->mem(1, rr).bytes <= ws_bytes) r = rr;
+        if (pl->mem(1, rr, scales).bytes <= ws_bytes) r = rr;
     if (r < 0) return false;
     int lo = 1, hi = nb;
     while (lo < hi) {
         int mid = (lo + hi + 1) / 2;
-        if (pl->mem(mid, r).bytes <= ws_bytes) lo = mid;
+        if (pl->mem(mid, r, scales).bytes <= ws_bytes) lo = mid;
         else hi = mid - 1;
     }
     r_out = r;
@@ -106,13 +106,14 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
     tn_plan* pl = const_cast<tn_plan*>(plan);
     tn_exec_stats es{};
     int r = shape_r, chunk = shape_chunk;
-    if (shape_chunk > 0 && pl->mem(shape_chunk, shape_r).bytes <= ws_bytes) {
+    const bool scales = precision == TN_SPLIT_FP16;
+    if (shape_chunk > 0 && pl->mem(shape_chunk, shape_r, scales).bytes <= ws_bytes) {
         // shape fixed by the caller (the serving loop reserved its memory)
-    } else if (!choose_shape(plan, nb, ws_bytes, ctx ? ctx->force_slice_block : -1, r, chunk)) {
+    } else if (!choose_shape(plan, nb, ws_bytes, ctx ? ctx->force_slice_block : -1, r, chunk, scales)) {
         set_error("one bitstring of this plan needs more workspace than available");
         return TN_ENOMEM;
     }
-    const MemPlan& mp = pl->mem(chunk, r);
+    const MemPlan& mp = pl->mem(chunk, r, scales);
     const int S = (int)p.sliced.size();
     const int R = 1 << r;
     const uint32_t low = (uint32_t)R - 1;
@@ -301,6 +302,8 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                 }
                 if (mp.scratch_off[si] != std::numeric_limits<size_t>::max())
                     g.P = reinterpret_cast<float2*>(ws + mp.scratch_off[si]);
+                if (scales && mp.scale_off[si] != std::numeric_limits<size_t>::max())
+                    g.X = reinterpret_cast<unsigned*>(ws + mp.scale_off[si]);
                 rc = ev_begin();
                 if (rc) return rc;
                 HIPCHK(ctx, launch_gemm(g, precision, stream));
@@ -460,8 +463,7 @@ int tn_contract_amplitudes(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bit
                            int32_t precision, void* hip_stream, double* out_re_im) {
     if (!ctx || !plan || !bits || !out_re_im) { set_error("null argument"); return TN_EINVAL; }
     if (nb <= 0) { set_error("nb must be positive"); return TN_EINVAL; }
-    if (precision != TN_FP32_4M && precision != TN_FP32_3M && precision != TN_SPLIT_BF16 &&
-        precision != TN_BF16_1TERM) {
+    if (!precision_ok(precision)) {
         set_error("precision mode not available");
         return TN_EINVAL;
     }
@@ -475,7 +477,7 @@ int tn_contract_amplitudes(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bit
     // workspace: the largest free region of the arena (all of it when the
     // serving loop is idle); wait for served batches to release memory when
     // not even one bitstring fits
-    const size_t need1 = const_cast<tn_plan*>(plan)->mem(1, 0).bytes;
+    const size_t need1 = const_cast<tn_plan*>(plan)->mem(1, 0, precision == TN_SPLIT_FP16).bytes;
     if (need1 > ctx->arena_bytes) {
         set_error("one bitstring of this plan needs more workspace than the arena holds");
         return TN_ENOMEM;
@@ -500,9 +502,15 @@ int tn_contract_amplitudes(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bit
 
 static bool pow2(long long x) { return x > 0 && (x & (x - 1)) == 0; }
 
+// split-K partials (rounded up to 256 bytes), then the row and column
+// maxima of the split fp16 products
+static size_t cgemm_partial_bytes(int M, int N, int K, int nbatch, int nb) {
+    return (gemm_scratch_elems(M, N, K, nbatch, nb) * 8 + 255) / 256 * 256;
+}
+
 size_t tn_kernel_cgemm_scratch_bytes(int32_t M, int32_t N, int32_t K, int32_t nbatch, int32_t nb) {
     if (!pow2(M) || !pow2(N) || !pow2(K) || nbatch <= 0 || nb <= 0) return 0;
-    return gemm_scratch_elems(M, N, K, nbatch, nb) * 8;
+    return cgemm_partial_bytes(M, N, K, nbatch, nb) + gemm_scale_words(M, N, K, nbatch, nb) * 4;
 }
 
 int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N, int32_t K,
@@ -514,13 +522,14 @@ int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N,
         set_error("bad gemm arguments (M, N, K must be powers of two)");
         return TN_EINVAL;
     }
-    const size_t need = gemm_scratch_elems(M, N, K, nbatch, nb) * 8;
+    if (!precision_ok(precision)) { set_error("precision mode not available"); return TN_EINVAL; }
+    const size_t part = gemm_scratch_elems(M, N, K, nbatch, nb) ? cgemm_partial_bytes(M, N, K, nbatch, nb) : 0;
+    const size_t words = precision == TN_SPLIT_FP16 ? gemm_scale_words(M, N, K, nbatch, nb) : 0;
+    const size_t need = part + words * 4;
     if (need > scratch_bytes || (need && !scratch)) {
         set_error("gemm needs " + std::to_string(need) + " bytes of scratch");
         return TN_EINVAL;
     }
-    if (precision != TN_FP32_4M && precision != TN_FP32_3M && precision != TN_SPLIT_BF16 &&
-        precision != TN_BF16_1TERM) { set_error("precision mode not available"); return TN_EINVAL; }
     GemmArgs g{};
     g.A = static_cast<const float2*>(A);
     g.B = static_cast<const float2*>(B);
@@ -530,6 +539,7 @@ int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N,
     g.nbatch = nbatch; g.nb = nb;
     g.sAb = sAb; g.sBb = sBb; g.sCb = sCb; g.sAi = sAi; g.sBi = sBi; g.sCi = sCi;
     g.P = static_cast<float2*>(scratch);
+    if (words) g.X = reinterpret_cast<unsigned*>(static_cast<char*>(scratch) + part);
     tn_ctx* none = nullptr;
     HIPCHK(none, launch_gemm(g, precision, static_cast<hipStream_t>(hip_stream)));
     return TN_OK;

@@ -135,7 +135,8 @@ static void scheduler(tn_ctx* ctx) {
             const bool heavy = plan->host.flops_total_per_b * total >= ctx->heavy_flops;
             if (heavy && heavy_busy >= ctx->max_heavy) continue;
             const size_t avail = largest_free(ctx);
-            const size_t need1 = plan->mem(1, 0).bytes;
+            const bool scales = head->precision == TN_SPLIT_FP16;
+            const size_t need1 = plan->mem(1, 0, scales).bytes;
             if (need1 > avail) {
                 if (!any_busy) {
                     // the whole arena is free and still too small
@@ -165,8 +166,8 @@ static void scheduler(tn_ctx* ctx) {
             // that shape's workspace
             int r = 0, ch = 0;
             const size_t cap = std::max(need1, std::min(avail, ctx->arena_bytes / 2));
-            choose_shape(plan, taken, cap, ctx->force_slice_block, r, ch);
-            const size_t bytes = plan->mem(ch, r).bytes;
+            choose_shape(plan, taken, cap, ctx->force_slice_block, r, ch, scales);
+            const size_t bytes = plan->mem(ch, r, scales).bytes;
             size_t off = 0;
             arena_alloc(ctx, bytes, &off);
             const int64_t t = now_ns();
@@ -252,12 +253,11 @@ int tn_submit(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int32_t nb
               uint64_t* ticket) {
     if (!ctx || !plan || !bits || !ticket) { set_error("null argument"); return TN_EINVAL; }
     if (nb <= 0) { set_error("nb must be positive"); return TN_EINVAL; }
-    if (precision != TN_FP32_4M && precision != TN_FP32_3M && precision != TN_SPLIT_BF16 &&
-        precision != TN_BF16_1TERM) { set_error("precision mode not available"); return TN_EINVAL; }
+    if (!precision_ok(precision)) { set_error("precision mode not available"); return TN_EINVAL; }
     if (ctx->poisoned) { set_error("context poisoned"); return TN_EDEVICE; }
     for (int i = 0; i < nb; ++i)
         if (bits[i] & ~plan->host.out_mask) { set_error("bitstring has a bit at a position >= n_qubits"); return TN_EINVAL; }
-    if (const_cast<tn_plan*>(plan)->mem(1, 0).bytes > ctx->arena_bytes) {
+    if (const_cast<tn_plan*>(plan)->mem(1, 0, precision == TN_SPLIT_FP16).bytes > ctx->arena_bytes) {
         set_error("one bitstring of this plan needs more workspace than the arena holds");
         return TN_ENOMEM;
     }

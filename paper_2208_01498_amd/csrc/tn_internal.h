@@ -106,11 +106,13 @@ struct MemPlan {
     std::vector<size_t> tensor_off;             // per tensor id (bytes), SIZE_MAX if none
     std::vector<size_t> permA_off, permB_off;   // per step, SIZE_MAX if none
     std::vector<size_t> scratch_off;            // per step split-K partials, SIZE_MAX if none
+    std::vector<size_t> scale_off;              // per step row/column maxima (split fp16 only)
+    bool scales = false;                        // laid out for the split fp16 products
     size_t acc_off = 0;                         // FP64 accumulators
     size_t bits_off = 0;                        // bitstrings
     size_t maps_off = 0;                        // per-step tables (none yet)
 };
-MemPlan plan_memory(const PlanHost& p, int chunk, int r);
+MemPlan plan_memory(const PlanHost& p, int chunk, int r, bool scales = false);
 
 struct DevicePlan;
 
@@ -124,7 +126,8 @@ struct tn_plan {
     std::mutex mcache;
     std::map<long long, tn::MemPlan> memcache;
     // workspace layout for `chunk` bitstrings and 2^r slices per pass
-    const tn::MemPlan& mem(int chunk, int r);
+    // (`scales`: with the per-step words of the split fp16 products)
+    const tn::MemPlan& mem(int chunk, int r, bool scales = false);
 };
 
 namespace tn {
@@ -198,7 +201,13 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb,
             int precision, hipStream_t stream, char* ws, size_t ws_bytes,
             double* out, tn_exec_stats* stats, int shape_r = 0, int shape_chunk = 0);
 // execution shape (log2 slices per pass, bitstrings per pass) for a workspace
-bool choose_shape(const tn_plan* plan, int nb, size_t ws_bytes, int force_r, int& r, int& chunk);
+bool choose_shape(const tn_plan* plan, int nb, size_t ws_bytes, int force_r, int& r, int& chunk,
+                  bool scales = false);
+// precision modes the executor runs
+inline bool precision_ok(int p) {
+    return p == TN_FP32_4M || p == TN_FP32_3M || p == TN_SPLIT_BF16 || p == TN_SPLIT_FP16 ||
+           p == TN_BF16_1TERM;
+}
 int64_t now_ns();
 // arena sub-allocation (callers hold ctx->smu)
 bool arena_alloc(tn_ctx* ctx, size_t bytes, size_t* off);

@@ -104,7 +104,7 @@ class Plan:
 
 
 def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
-              n_circles=24, trials=1, objective="time", coarsen=0, projector=None,
+              n_circles=24, trials=3, objective="time", coarsen=0, projector=None,
               top_exact=13):
     """Build a plan.  ``n_slices``: number of sliced labels (log2 of the slice
     count), or None to slice until the widest per-slice intermediate is at
@@ -117,6 +117,7 @@ def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
     forms = [False]
     if projector is None and any(len(g.qubits) == 2 and _is_swap_diag(g.matrix) for g in circ.gates):
         forms.append(True)
+    do_slice = bool(n_slices) or target_width is not None
     best = None
     for swap_relabel in forms:
         if projector is None:
@@ -130,17 +131,23 @@ def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
             if top_exact:
                 root = refine_top(root, tb, B=B, frontier=top_exact)
             steps = tree_steps(root, len(net.factors))
-            st = plan_stats(net, steps, B=1)
-            if best is None or st["flops"] < best[0]:
-                best = (st["flops"], steps, net)
-    steps, net = best[1], best[2]
-    sliced = []
+            # Trials compete on the cost that is actually executed: the
+            # summed cost over all slices when slicing is asked for, the
+            # unsliced Eq. (3) cost otherwise.
+            sliced, sm = [], None
+            if steps:
+                sm = SliceModel(net, steps, B=B, objective=objective)
+                if do_slice:
+                    sliced, _, _ = sm.greedy(n_slices=n_slices if n_slices else None,
+                                             target_width=target_width)
+                cost = sm.evaluate(sliced, ordered=True)[0]
+            else:
+                cost = plan_stats(net, steps, B=1)["flops"]
+            if best is None or cost < best[0]:
+                best = (cost, steps, net, sliced, sm)
+    _, steps, net, sliced, sm = best
     total = None
     predicted = None
-    sm = SliceModel(net, steps, B=B, objective=objective) if steps else None
-    if steps and (n_slices or target_width is not None):
-        sliced, _, width = sm.greedy(n_slices=n_slices if n_slices else None,
-                                     target_width=target_width)
     if sm is not None:
         predicted, _ = sm.evaluate(sliced, ordered=True)
         total = sm.last_flops
