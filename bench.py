@@ -37,12 +37,12 @@ EXEC = {"fp32": 1.0, "fp32_3m": 0.75, "bf16x3": 3.0, "fp16x3": 3.0, "bf16x1": 1.
 # changed kernel or plan reports null until it is measured again.
 TRAFFIC = [
     {"class": "cgemm_mfma_128x128", "precision": "fp32_3m", "source": "gemm.hip",
-     "source_sha256": "0ac99b6dd588fc8a0a0f79a04cb87066cc3bfac954735e2e6dd5751fe3c2381a",
-     "chunk": 26, "flops_per_amplitude": 40288685565267.0,
-     "bytes_per_launch": 1.736e11,
-     "note": "HBM fetch 1.592e11 + write 1.438e10 bytes per launch (the 141 launches of one "
+     "source_sha256": "77056396223391fc48bc7ef95266dbd0aca343784705165d4cd801bea0c97559",
+     "chunk": 26, "flops_per_amplitude": 40162127117832.0,
+     "bytes_per_launch": 1.802e11,
+     "note": "HBM fetch 1.678e11 + write 1.238e10 bytes per launch (the 153 launches of one "
              "timed step; FETCH_SIZE x2.0 and WRITE_SIZE x1.0 from a 1 GiB copy); algorithmic "
-             "1.847e10"},
+             "1.637e10"},
 ]
 
 
