@@ -293,3 +293,15 @@ def test_exact_top_order_never_costs_more(name, mk):
     spec = ref.order_spec()
     got = pairwise_amplitudes(circ, words, order=spec, sliced=spec["sliced"])
     assert np.max(np.abs(got - statevector_amplitudes(circ, words))) <= 1e-12
+
+
+def test_seed_trials_keep_the_cheapest_sliced_plan():
+    """make_plan builds one hierarchy per seed (Algorithm 1 is randomised),
+    refines and slices each, and keeps the least total cost over all
+    slices: never more than any single seed's plan."""
+    circ = lattice_circuit(4, 5, 10, 480, "haar", "cz")
+    kw = dict(n_slices=3, B=4)
+    kept = make_plan(circ, trials=3, **kw).stats["total_flops_per_b"]
+    singles = [make_plan(circ, seed=s, trials=1, **kw).stats["total_flops_per_b"] for s in range(3)]
+    assert kept <= min(singles) * (1 + 1e-12)
+    assert kept in singles
