@@ -206,7 +206,8 @@ def paper_families_bench(args):
     the counted cost of each plan (the paper's measure: real flops per
     amplitude, Eq. (3)) beside the measured time."""
     import numpy as np
-    from circuits import paper_iqp_circuit, sycamore_type_circuit, random_bitstrings
+    from circuits import paper_family_instances, random_bitstrings
+    from paper_2208_01498_amd.planner.bounds import circuit_bounds
     from paper_2208_01498_amd.planner.plan import make_plan
     from paper_2208_01498_amd import binding as B
     import torch
@@ -215,9 +216,7 @@ def paper_families_bench(args):
     prec = B.PRECISIONS[args.precision]
     rows = []
     for L in range(4, 9):
-        for fam, circ in (("iqp_T=L^2_gamma=3", paper_iqp_circuit(L, L * L, 5200 + L)),
-                          ("sycamore_type_q=5_p=0.88", sycamore_type_circuit(L, 5, 0.88, 5300 + L)),
-                          ("sycamore_type_q=5_p=0.5", sycamore_type_circuit(L, 5, 0.5, 5400 + L))):
+        for fam, circ, T in paper_family_instances(L):
             words = random_bitstrings(circ.n, 64, 5500 + L)
             t = time.perf_counter()
             plan = make_plan(circ, n_slices=None, target_width=30, B=len(words))
@@ -232,7 +231,9 @@ def paper_families_bench(args):
             rows.append({"family": fam, "L": L, "n": circ.n, "gates": len(circ.gates),
                          "flops_per_amplitude": plan.stats["total_flops_per_b"],
                          "max_rank": plan.stats["max_bits"], "slices": 1 << len(plan.sliced),
-                         "plan_s": t_plan, "amplitudes_per_s": len(words) / el})
+                         "plan_s": t_plan, "amplitudes_per_s": len(words) / el,
+                         "log2_ops_plan": math.log2(plan.stats["total_flops_per_b"] / 4.0)})
+            rows[-1].update(circuit_bounds(circ, T))
             log(json.dumps(rows[-1]))
             eng.unload(h)
     print(json.dumps({"metric": "paper families: counted flops and measured amplitudes/s",

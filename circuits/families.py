@@ -173,6 +173,16 @@ def sycamore_type_circuit(L, periods, p_inaccessible, seed):
                    {"L": L, "periods": periods, "p": p_inaccessible, "seed": seed})
 
 
+def paper_family_instances(L):
+    """One seeded realization per family of the paper's examples at size L:
+    (name, circuit, time steps T) for the IQP family (T = L^2, gamma = 3)
+    and the Sycamore-type family (5 periods of 8 cycles; qubits
+    inaccessible with probability 0.88, and 0.5 as a denser variant)."""
+    return [("iqp_T=L^2_gamma=3", paper_iqp_circuit(L, L * L, 5200 + L), L * L),
+            ("sycamore_type_q=5_p=0.88", sycamore_type_circuit(L, 5, 0.88, 5300 + L), 40),
+            ("sycamore_type_q=5_p=0.5", sycamore_type_circuit(L, 5, 0.5, 5400 + L), 40)]
+
+
 def stack3d_circuit(X, Y, Z, layers, seed, name=""):
     """(2+1)-dimensional-style random circuit on an X x Y x Z qubit stack
     (q = x + X*y + X*Y*z).  Each layer picks an axis uniformly from {x,y,z}

@@ -1,0 +1,163 @@
+"""The paper's closed-form runtime bounds, evaluated for a given network or
+circuit, so that a plan's counted cost (Eq. (3) summed over its steps) can be
+reported next to them.  Host-side reporting only: nothing here is on the
+executed path.
+
+All values are log2 of a number of scalar operations (multiplications and
+additions), the paper's unit; the bounds themselves overflow floats.
+
+* Theorem 1 (and its closed form, Eq. (5)): n tensors of at most M entries
+  embedded in R^d with at most k spheres over any point.
+* Eq. (4): the level-by-level sum that Eq. (5) majorises by a geometric sum.
+* The planar variant after the Planar Separator Theorem (parts at most 2n/3,
+  c_PST sqrt(n) separator vertices).
+* Theorem 2: a (d+1)-dimensional circuit with f_i two-qubit gates on qubit
+  i, gate range l and qubit spacing r; and its tighter d = 2
+  nearest-neighbour form through the planar variant.
+* The two baselines the paper compares against: side-wise (left-to-right)
+  contraction of an L^d lattice, and explicit time evolution of the state.
+
+Reading of the planar d = 2 statement: the proof puts identity tensors of
+M = 4^4 entries at line crossings, which makes the exponent 8 a_2' sqrt(n')
+with n' = sum_i f_i (2 + f_i / 2); the statement of Theorem 2 prints 4 a_2'.
+`theorem2_planar_log2` takes log2 M as an argument (8 by default, the
+proof's M; 4 reproduces the printed exponent).
+"""
+import math
+
+from .ssa import C_D
+
+C_PST = 1.971      # Planar Separator Theorem coefficient (an upper value)
+
+
+def poly_exponent(d):
+    """Exponent of n in Theorem 1's prefactor: 1 / log2((d+2)/(d+1))."""
+    return 1.0 / math.log2((d + 2) / (d + 1))
+
+
+def a_coeff(d):
+    """a_d = c_d / [2 - 2 ((d+1)/(d+2))^(1-1/d)] (Theorem 1)."""
+    return C_D[d] / (2.0 - 2.0 * ((d + 1) / (d + 2)) ** (1.0 - 1.0 / d))
+
+
+def a_planar():
+    """a_2' = c_PST / (2 - 2 sqrt(2/3)) (planar variant)."""
+    return C_PST / (2.0 - 2.0 * math.sqrt(2.0 / 3.0))
+
+
+def theorem1_log2(n, M, k, d):
+    """log2 of 2 n^{1/log2((d+2)/(d+1))} M^{a_d k^{1/d} n^{1-1/d}}."""
+    return (1.0 + poly_exponent(d) * math.log2(n)
+            + a_coeff(d) * k ** (1.0 / d) * n ** (1.0 - 1.0 / d) * math.log2(M))
+
+
+def hierarchy_levels(n, d):
+    """Upper limit of the number of levels z in Eq. (4):
+    1 + log2(n) / log2((d+2)/(d+1))."""
+    return 1.0 + math.log2(n) / math.log2((d + 2) / (d + 1))
+
+
+def eq4_level_exponent(n, k, d, level):
+    """Exponent of M in the level-`level` term of Eq. (4):
+    (1/2) sum_{j=1}^{level+1} c_d k^{1/d} [n ((d+1)/(d+2))^{j-1}]^{1-1/d}."""
+    rho = (d + 1) / (d + 2)
+    return 0.5 * sum(C_D[d] * k ** (1.0 / d) * (n * rho ** (j - 1)) ** (1.0 - 1.0 / d)
+                     for j in range(1, level + 2))
+
+
+def eq4_sum_log2(n, M, k, d, z=None):
+    """log2 of the level sum of Eq. (4) (without the bottom term
+    2^z M^{O(1)}, whose constant the paper leaves open):
+    sum_{l=0}^{z-1} 2^{l+1} M^{(1/2) sum_{j=1}^{l+1} c_d k^{1/d}
+    [n ((d+1)/(d+2))^{j-1}]^{1-1/d}}."""
+    if z is None:
+        z = int(math.floor(hierarchy_levels(n, d)))
+    rho = (d + 1) / (d + 2)
+    lm = math.log2(M)
+    terms = []
+    inner = 0.0
+    for level in range(z):
+        j = level + 1
+        inner += C_D[d] * k ** (1.0 / d) * (n * rho ** (j - 1)) ** (1.0 - 1.0 / d)
+        terms.append(level + 1 + 0.5 * inner * lm)
+    top = max(terms)
+    return top + math.log2(sum(2.0 ** (t - top) for t in terms))
+
+
+def planar_log2(n, M):
+    """log2 of 2 n^{1/log2(3/2)} M^{a_2' sqrt(n)} (planar variant)."""
+    return 1.0 + math.log2(n) / math.log2(1.5) + a_planar() * math.sqrt(n) * math.log2(M)
+
+
+def theorem2_log2(f, d, l_over_r):
+    """log2 of [2 sum f]^{1/log2((d+2)/(d+1))} 2^{1 + 8 a_d (1 + l/r) F^{1/d}
+    (sum f)^{1-1/d}}, f the two-qubit gate count per qubit, F = max f."""
+    S = float(sum(f))
+    F = float(max(f))
+    return (poly_exponent(d) * math.log2(2.0 * S) + 1.0
+            + 8.0 * a_coeff(d) * (1.0 + l_over_r) * F ** (1.0 / d) * S ** (1.0 - 1.0 / d))
+
+
+def planar_vertices(f):
+    """Vertex count of the planar graph of the d = 2 nearest-neighbour
+    proof: sum_i f_i (2 + f_i / 2)."""
+    return float(sum(fi * (2.0 + fi / 2.0) for fi in f))
+
+
+def theorem2_planar_log2(f, log2_M=8.0):
+    """The d = 2 nearest-neighbour bound through the planar variant, with
+    n' = planar_vertices(f) and tensors of 2^log2_M entries."""
+    n = planar_vertices(f)
+    return 1.0 + math.log2(n) / math.log2(1.5) + a_planar() * math.sqrt(n) * log2_M
+
+
+def sidewise_log2(F, L, d):
+    """log2 of 2^{1 + 4 F L^{d-1}} L: left-to-right contraction of an L^d
+    lattice."""
+    return 1.0 + 4.0 * F * L ** (d - 1) + math.log2(L)
+
+
+def explicit_log2(T, N, idle=0):
+    """log2 of T N 2^{2 + N - idle}: explicit time evolution of the state
+    (qubits no two-qubit gate touches stay out of the state)."""
+    return math.log2(T) + math.log2(N) + 2.0 + N - idle
+
+
+def circuit_profile(circ):
+    """(f, F, l/r, idle): two-qubit gate count per qubit, its maximum, the
+    largest gate range over the smallest qubit spacing, and the number of
+    qubits no two-qubit gate touches."""
+    import numpy as np
+    f = [0] * circ.n
+    lmax = 0.0
+    pos = np.asarray(circ.positions, dtype=float)
+    for g in circ.gates:
+        if len(g.qubits) == 2:
+            a, b = g.qubits
+            f[a] += 1
+            f[b] += 1
+            lmax = max(lmax, float(np.linalg.norm(pos[a] - pos[b])))
+    diff = pos[:, None, :] - pos[None, :, :]
+    dist = np.sqrt((diff ** 2).sum(-1))
+    dist[np.arange(circ.n), np.arange(circ.n)] = np.inf
+    r = float(dist.min()) if circ.n > 1 else 1.0
+    idle = sum(1 for x in f if x == 0)
+    return f, max(f) if f else 0, (lmax / r if lmax > 0 else 1.0), idle
+
+
+def circuit_bounds(circ, T):
+    """The bounds for a circuit of T time steps on a d-dimensional layout
+    (d = 2 for lattices): a dict of log2 values (None where a bound does
+    not apply)."""
+    f, F, lr, idle = circuit_profile(circ)
+    d = int(circ.positions.shape[1])
+    out = {"sum_f": int(sum(f)), "F": int(F), "l_over_r": lr, "idle": idle,
+           "log2_explicit": explicit_log2(T, circ.n, idle)}
+    if F == 0:
+        out.update(log2_theorem2=None, log2_theorem2_planar=None, log2_sidewise=None)
+        return out
+    out["log2_theorem2"] = theorem2_log2(f, max(d, 2), lr)
+    out["log2_theorem2_planar"] = theorem2_planar_log2(f) if d == 2 and lr <= 1.0 + 1e-9 else None
+    L = round(circ.n ** (1.0 / d))
+    out["log2_sidewise"] = sidewise_log2(F, L, d) if L ** d == circ.n else None
+    return out

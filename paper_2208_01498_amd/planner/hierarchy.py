@@ -185,6 +185,63 @@ class TreeBuilder:
                 best = sc
         return best[1], best[2]
 
+    def components(self, idx):
+        """Connected components of the leaves `idx` (leaves sharing a
+        contracted label are connected; output labels connect nothing)."""
+        parent = {i: i for i in idx}
+
+        def find(x):
+            while parent[x] != x:
+                parent[x] = parent[parent[x]]
+                x = parent[x]
+            return x
+
+        for l, us in self.users.items():
+            if self.is_out[l]:
+                continue
+            us = [u for u in us if u in parent]
+            for u in us[1:]:
+                ra, rb = find(us[0]), find(u)
+                if ra != rb:
+                    parent[ra] = rb
+        comps = {}
+        for i in idx:
+            comps.setdefault(find(i), []).append(i)
+        return sorted(comps.values(), key=min)
+
+    def component_groups(self):
+        """Leaves grouped for separate hierarchies: one group per connected
+        component larger than a bottom cluster; a small component (say a
+        diagonal factor on output labels only) joins a large one that shares
+        one of its output labels (else the largest), so that it stays placed
+        among its neighbours."""
+        comps = self.components(list(range(len(self.facs))))
+        big = [c for c in comps if len(c) > self.bottom]
+        if len(big) < 2:
+            return [sorted(range(len(self.facs)))]
+        owner = {}
+        for gi, c in enumerate(big):
+            for i in c:
+                owner[i] = gi
+        groups = [list(c) for c in big]
+        largest = max(range(len(big)), key=lambda g: len(big[g]))
+        for c in comps:
+            if len(c) > self.bottom:
+                continue
+            target = largest
+            for i in c:
+                for l in self.facs[i].labels:
+                    if self.is_out[l]:
+                        hit = [owner[u] for u in self.users[l] if u in owner]
+                        if hit:
+                            target = hit[0]
+                            break
+                else:
+                    continue
+                break
+            groups[target].extend(c)
+        return [sorted(g) for g in groups]
+
     def build(self, idx=None):
         if idx is None:
             idx = list(range(len(self.facs)))

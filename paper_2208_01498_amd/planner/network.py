@@ -172,7 +172,7 @@ def build_network(circ, simplify=True, swap_relabel=False, coarsen=0):
     return net
 
 
-def build_doubled_network(circ, traced=(), simplify=True):
+def build_doubled_network(circ, traced=(), simplify=True, swap_relabel=False):
     """The paper's quantity c = <0|U^dag (x)_q P_q U|0> for product
     projectors (the problem statement around Theorem 2): the network of U
     and its complex conjugate, with P_q = |x_q><x_q| on the qubits not in
@@ -182,7 +182,7 @@ def build_doubled_network(circ, traced=(), simplify=True):
     of qubits gives the marginal probability of the others.  Gate ids of the
     conjugate layer are offset by the number of gates."""
     traced = set(int(q) for q in traced)
-    one = build_network(circ, simplify=simplify)
+    one = build_network(circ, simplify=simplify, swap_relabel=swap_relabel)
     off = max(one.labels) + 1
     G = len(circ.gates)
     labels = {}

@@ -115,7 +115,7 @@ def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
     is chosen exactly (0 keeps the hierarchy's order everywhere)."""
     from .network import _is_swap_diag, build_doubled_network
     forms = [False]
-    if projector is None and any(len(g.qubits) == 2 and _is_swap_diag(g.matrix) for g in circ.gates):
+    if any(len(g.qubits) == 2 and _is_swap_diag(g.matrix) for g in circ.gates):
         forms.append(True)
     do_slice = bool(n_slices) or target_width is not None
     best = None
@@ -123,13 +123,20 @@ def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
         if projector is None:
             net = build_network(circ, swap_relabel=swap_relabel, coarsen=coarsen)
         else:
-            net = build_doubled_network(circ, traced=projector)
+            net = build_doubled_network(circ, traced=projector, swap_relabel=swap_relabel)
         for t in range(trials):
             tb = TreeBuilder(net, np.random.Generator(np.random.PCG64(seed + t)),
                              bottom=bottom, n_circles=n_circles)
-            root = tb.build()
-            if top_exact:
-                root = refine_top(root, tb, B=B, frontier=top_exact)
+            # a network that falls apart (the two layers of a doubled
+            # network with every qubit projected) gets one hierarchy and one
+            # exact top order per component; component results multiply last
+            roots = []
+            for grp in tb.component_groups():
+                r = tb.build(grp)
+                if top_exact:
+                    r = refine_top(r, tb, B=B, frontier=top_exact)
+                roots.append(r)
+            root = roots[0] if len(roots) == 1 else tb.greedy(roots)
             steps = tree_steps(root, len(net.factors))
             # Trials compete on the cost that is actually executed: the
             # summed cost over all slices when slicing is asked for, the

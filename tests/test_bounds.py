@@ -1,0 +1,107 @@
+"""Pins for the paper's closed-form bounds (planner-side reporting): each
+formula is checked against a second route to the same number or against an
+inequality the paper states."""
+import math
+
+import numpy as np
+import pytest
+
+from circuits import Circuit, Gate, CZ, lattice_circuit, product_circuit, paper_family_instances
+from paper_2208_01498_amd.planner import bounds as bd
+
+
+def test_a2_closed_form_and_planar_is_smaller():
+    # the planar-variant paragraph states a_2' < a_2 = c_2 / (2 - 2 sqrt(3/4))
+    assert abs(bd.a_coeff(2) - 2.0 / (2.0 - math.sqrt(3.0))) < 1e-12
+    assert bd.a_planar() < bd.a_coeff(2)
+
+
+@pytest.mark.parametrize("d", [2, 3, 4, 5])
+def test_eq5_is_the_limit_of_the_eq4_exponents(d):
+    """The level exponents of Eq. (4), summed level by level, increase to
+    the geometric-sum value a_d k^{1/d} n^{1-1/d} that Eq. (5) uses: a wrong
+    a_d (factor, ratio or power) breaks the limit."""
+    n, k = 5000.0, 6.0
+    lim = bd.a_coeff(d) * k ** (1.0 / d) * n ** (1.0 - 1.0 / d)
+    prev = 0.0
+    for level in (0, 1, 5, 20, 100):
+        e = bd.eq4_level_exponent(n, k, d, level)
+        assert prev < e < lim
+        prev = e
+    assert abs(bd.eq4_level_exponent(n, k, d, 4000) - lim) <= 1e-9 * lim
+
+
+@pytest.mark.parametrize("n,M,k,d", [(200, 16, 4, 2), (5000, 16, 8, 2), (3000, 256, 5, 3)])
+def test_eq4_sum_below_eq5(n, M, k, d):
+    """Each Eq. (4) term is 2^{l+1} M^{e_l} with e_l below the Eq. (5)
+    exponent, and sum_{l<z} 2^{l+1} < 2^{z+1} <= 4 n^{1/log2((d+2)/(d+1))}:
+    the level sum stays below Eq. (5) times 2."""
+    zmax = int(math.floor(bd.hierarchy_levels(n, d)))
+    for z in (1, zmax // 2, zmax):
+        assert bd.eq4_sum_log2(n, M, k, d, z) < bd.theorem1_log2(n, M, k, d) + 1.0
+
+
+@pytest.mark.parametrize("d,lr", [(2, 1.0), (2, 2.0), (3, 1.0)])
+def test_theorem2_is_theorem1_on_the_circuit_network(d, lr):
+    """Theorem 2 by its proof: Theorem 1 with n = 2 sum f tensors of M = 16
+    entries and k = 2 F (1 + l/r)^d overlapping spheres."""
+    rng = np.random.Generator(np.random.PCG64(7))
+    f = list(rng.integers(1, 30, size=40))
+    n = 2.0 * sum(f)
+    k = 2.0 * max(f) * (1.0 + lr) ** d
+    assert abs(bd.theorem2_log2(f, d, lr) - bd.theorem1_log2(n, 16, k, d)) <= 1e-9 * bd.theorem1_log2(n, 16, k, d)
+
+
+def test_planar_form_and_vertex_count():
+    # two qubits with 2 and 4 gates: 2*(2 + 1) + 4*(2 + 2) = 22 planar vertices
+    assert bd.planar_vertices([2, 4]) == 22.0
+    for lm in (4.0, 8.0):
+        assert abs(bd.theorem2_planar_log2([2, 4], lm) - bd.planar_log2(22.0, 2.0 ** lm)) < 1e-12
+
+
+@pytest.mark.parametrize("F,L,d", [(3, 8, 2), (10, 40, 2), (2, 5, 3)])
+def test_sidewise_two_forms(F, L, d):
+    # 2^{1 + 4 F L^{d-1}} L = 2^{1 + 4 F N^{1-1/d}} N^{1/d} with N = L^d
+    N = float(L ** d)
+    alt = 1.0 + 4.0 * F * N ** (1.0 - 1.0 / d) + math.log2(N) / d
+    assert abs(bd.sidewise_log2(F, L, d) - alt) <= 1e-9 * alt
+
+
+def test_explicit_bound_covers_a_counted_state_vector_run():
+    """T layers of disjoint two-qubit gates on N qubits: applying a 4 x 4
+    matrix to each of the 2^{N-2} blocks of the state costs 16 products and
+    as many sums per block, 2^{N+3} operations per gate, at most N/2 gates a
+    layer: at most T N 2^{N+2}, the explicit-evolution bound."""
+    N, T = 10, 6
+    pos = np.array([[0.0, float(q)] for q in range(N)])
+    gates = []
+    for t in range(T):
+        for a in range(t % 2, N - 1, 2):
+            gates.append(Gate((a, a + 1), CZ.copy(), "CZ"))
+    c = Circuit(N, gates, pos)
+    ops = sum(2.0 ** (N + 3) for g in c.gates)
+    assert math.log2(ops) <= bd.explicit_log2(T, N)
+
+
+def test_circuit_profile_cases():
+    f, F, lr, idle = bd.circuit_profile(product_circuit(6, 2, 1))
+    assert F == 0 and idle == 6
+    pos = np.array([[0.0, 0.0], [0.0, 1.0], [0.0, 3.0]])
+    c = Circuit(3, [Gate((0, 1), CZ.copy()), Gate((0, 1), CZ.copy()), Gate((1, 2), CZ.copy())], pos)
+    f, F, lr, idle = bd.circuit_profile(c)
+    assert f == [2, 3, 1] and F == 3 and idle == 0
+    assert abs(lr - 2.0) < 1e-12          # range 2 over spacing 1
+
+
+def test_counted_plans_below_theorem2():
+    """The paper notes that the hierarchy's counted cost is at least as good
+    as the Theorem 2 bound: so is this planner's, for the paper's families
+    at L = 4 (one amplitude and the doubled network of its quantity c)."""
+    from paper_2208_01498_amd.planner.report import counted_log2
+    for name, circ, T in paper_family_instances(4):
+        b = bd.circuit_bounds(circ, T)
+        amp, _ = counted_log2(circ)
+        dbl, _ = counted_log2(circ, projector=())
+        assert amp <= dbl <= b["log2_theorem2"], name
+        if b["log2_theorem2_planar"] is not None:
+            assert dbl <= b["log2_theorem2_planar"], name

@@ -235,12 +235,14 @@ def _projectors(n, word, traced):
 
 
 @pytest.mark.parametrize("traced", [(), (0, 5), (1, 2, 3, 7, 9)])
-def test_projector_network_matches_doubled_oracle(traced):
+@pytest.mark.parametrize("twoq", ["cz", "fsim"])
+def test_projector_network_matches_doubled_oracle(traced, twoq):
     """The planner's network of C and its conjugate (the paper's
     <0|C^dag (x) P_q C|0>) contracted in the plan's order equals the oracle's
-    doubled expectation, for projected and traced qubits."""
+    doubled expectation, for projected and traced qubits (fSim(pi/2, pi/6)
+    also in its SWAP-times-diagonal form)."""
     from oracle import doubled_expectation
-    circ = lattice_circuit(3, 4, 5, 450, "haar", "cz")
+    circ = lattice_circuit(3, 4, 5, 450, "haar" if twoq == "cz" else "sqrt", twoq)
     plan = make_plan(circ, n_slices=0, B=2, projector=traced)
     for w in random_bitstrings(circ.n, 3, 451):
         w = int(w) & ~sum(1 << q for q in traced)
@@ -305,3 +307,23 @@ def test_seed_trials_keep_the_cheapest_sliced_plan():
     singles = [make_plan(circ, seed=s, trials=1, **kw).stats["total_flops_per_b"] for s in range(3)]
     assert kept <= min(singles) * (1 + 1e-12)
     assert kept in singles
+
+
+@pytest.mark.parametrize("traced", [(), (2, 6)])
+def test_doubled_network_swap_form_matches_oracle(traced):
+    """The doubled network built with fSim(pi/2, pi/6) as a wire exchange
+    times a diagonal factor (both layers) gives the oracle's doubled
+    expectation, contracted in a hierarchy order."""
+    import numpy as np
+    from oracle import doubled_expectation
+    from paper_2208_01498_amd.planner.network import build_doubled_network
+    from paper_2208_01498_amd.planner.hierarchy import TreeBuilder, tree_steps
+    circ = lattice_circuit(3, 3, 4, 455, "sqrt", "fsim")
+    net = build_doubled_network(circ, traced=traced, swap_relabel=True)
+    root = TreeBuilder(net, np.random.Generator(np.random.PCG64(1)), bottom=8).build()
+    steps = tree_steps(root, len(net.factors))
+    for w in random_bitstrings(circ.n, 2, 456):
+        w = int(w) & ~sum(1 << q for q in traced)
+        got = _contract_net_host(net, steps, w)
+        ref = doubled_expectation(circ, _projectors(circ.n, w, traced), method="statevector")
+        assert abs(got - ref) <= 1e-12 * max(abs(ref), 1e-300)
