@@ -36,8 +36,9 @@ class Node:
 
 
 class TreeBuilder:
-    def __init__(self, net, rng, bottom=8, n_circles=24, radius=0.26):
+    def __init__(self, net, rng, bottom=8, n_circles=24, radius=0.26, centerpoint="radon"):
         self.net = net
+        self.centerpoint = centerpoint
         self.rng = rng
         self.bottom = bottom
         self.n_circles = n_circles
@@ -255,7 +256,8 @@ class TreeBuilder:
             radii = np.full(len(idx), self.radius)
             d = pts.shape[1]
             k = max_overlap(pts, radii)
-            cands = ssa_candidates(pts, radii, self.rng, self.n_circles) + plane_candidates(pts)
+            cands = (ssa_candidates(pts, radii, self.rng, self.n_circles, self.centerpoint)
+                     + plane_candidates(pts))
             best = None
             idx_arr = np.array(idx)
             for sep in cands:

@@ -105,14 +105,16 @@ class Plan:
 
 def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
               n_circles=24, trials=3, objective="time", coarsen=0, projector=None,
-              top_exact=13):
+              top_exact=13, centerpoint="lp"):
     """Build a plan.  ``n_slices``: number of sliced labels (log2 of the slice
     count), or None to slice until the widest per-slice intermediate is at
     most ``target_width`` (log2 elements, batch included).  ``projector``:
     None for amplitudes <x|C|0>; otherwise the set of traced qubits of the
     projector quantity <0|C^dag (x)_q P_q C|0> (P_q = |x_q><x_q| elsewhere).
     ``top_exact``: size of the frontier below the root whose pairwise order
-    is chosen exactly (0 keeps the hierarchy's order everywhere)."""
+    is chosen exactly (0 keeps the hierarchy's order everywhere).
+    ``centerpoint``: Algorithm 1's centerpoint by the LP over a random
+    subset ("lp", the paper's route) or by iterated Radon points ("radon")."""
     from .network import _is_swap_diag, build_doubled_network
     forms = [False]
     if any(len(g.qubits) == 2 and _is_swap_diag(g.matrix) for g in circ.gates):
@@ -126,7 +128,7 @@ def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
             net = build_doubled_network(circ, traced=projector, swap_relabel=swap_relabel)
         for t in range(trials):
             tb = TreeBuilder(net, np.random.Generator(np.random.PCG64(seed + t)),
-                             bottom=bottom, n_circles=n_circles)
+                             bottom=bottom, n_circles=n_circles, centerpoint=centerpoint)
             # a network that falls apart (the two layers of a doubled
             # network with every qubit projected) gets one hierarchy and one
             # exact top order per component; component results multiply last

@@ -3,9 +3,10 @@ the separator checks of the Sphere Separator Theorem, Eqs. (1)-(2).
 
 Steps, in the paper's order:
   1. stereographic projection Pi of the sphere centres onto S^d in R^{d+1};
-  2. an approximate centerpoint c of the projected points (here: iterated
-     Radon points of random subsets, a standard randomized centerpoint
-     approximation, in place of the LP on random subsets);
+  2. an approximate centerpoint c of the projected points: the paper's
+     route, a linear program over a random subset (`centerpoint_lp`), or
+     iterated Radon points of random subsets (`centerpoint`, a standard
+     randomized approximation);
   3. an orthogonal R with R c = (0, ..., 0, |c|);
   4. the dilation D_alpha = Pi o (alpha 1) o Pi^{-1},
      alpha = sqrt((1 - |c|)/(1 + |c|));
@@ -59,6 +60,49 @@ def centerpoint(P, rng, rounds=None):
     while len(pts) > 1:
         pts = np.array([radon_point(pts[i:i + g]) for i in range(0, len(pts), g)])
     return pts[0]
+
+
+def centerpoint_lp(P, rng, sample=16):
+    """Centerpoint of a random subset of the points by linear programming.
+    A point of R^D is a centerpoint of a set of a points when every closed
+    halfspace containing it holds at least a/(D+1) of them; equivalently it
+    lies in every closed halfspace holding more than a D/(D+1) of them.  The
+    halfspaces used are those bounded by hyperplanes through D of the
+    subset's points (both sides); the LP finds a point in their
+    intersection, which Helly's theorem makes non-empty.  Falls back to
+    iterated Radon points if the solver finds none (degenerate subsets)."""
+    from itertools import combinations
+    from scipy.optimize import linprog
+    m, D = P.shape
+    S = P[rng.choice(m, size=min(sample, m), replace=False)]
+    a = len(S)
+    if a <= D:
+        return S.mean(axis=0)
+    thr = a * D / (D + 1)
+    rows, rhs = [], []
+    scale = max(1.0, float(np.max(np.abs(S))))
+    for comb in combinations(range(a), D):
+        Q = S[list(comb)]
+        M = Q[1:] - Q[0]
+        _, sv, vt = np.linalg.svd(M, full_matrices=True)
+        if len(sv) and sv.min() < 1e-9 * scale:
+            continue                       # the D points span less than a hyperplane
+        nrm = vt[-1]
+        off = float(nrm @ Q[0])
+        s = S @ nrm - off
+        tol = 1e-12 * scale
+        for sign in (1.0, -1.0):
+            if np.count_nonzero(sign * s >= -tol) > thr:
+                # sign * (nrm . c - off) >= 0
+                rows.append(-sign * nrm)
+                rhs.append(-sign * off)
+    if not rows:
+        return centerpoint(P, rng)
+    res = linprog(np.zeros(D), A_ub=np.array(rows), b_ub=np.array(rhs),
+                  bounds=[(None, None)] * D, method="highs")
+    if res.status != 0:
+        return centerpoint(P, rng)
+    return res.x
 
 
 def _householder_to_pole(c):
@@ -138,16 +182,18 @@ def eq_checks(side, d, k):
     return ok1, ok2
 
 
-def ssa_candidates(pts, radii, rng, n_circles=24):
+def ssa_candidates(pts, radii, rng, n_circles=24, method="radon"):
     """Separator candidates from Algorithm 1 (one centerpoint, several random
-    great circles).  Returns a list of separators (see classify)."""
+    great circles).  Returns a list of separators (see classify).
+    `method`: centerpoint by iterated Radon points ("radon") or by the LP
+    over a random subset ("lp")."""
     m, d = pts.shape
     mu = pts.mean(axis=0)
     sc = np.max(np.linalg.norm(pts - mu, axis=1))
     sc = sc if sc > 0 else 1.0
     x = (pts - mu) / sc
     y = stereo(x)                                            # step 1
-    c = centerpoint(y, rng)                                  # step 2
+    c = centerpoint_lp(y, rng) if method == "lp" else centerpoint(y, rng)   # step 2
     R = _householder_to_pole(c)                              # step 3
     nc = min(np.linalg.norm(c), 1 - 1e-9)
     alpha = np.sqrt((1 - nc) / (1 + nc))                     # step 4

@@ -327,3 +327,32 @@ def test_doubled_network_swap_form_matches_oracle(traced):
         got = _contract_net_host(net, steps, w)
         ref = doubled_expectation(circ, _projectors(circ.n, w, traced), method="statevector")
         assert abs(got - ref) <= 1e-12 * max(abs(ref), 1e-300)
+
+
+@pytest.mark.parametrize("D", [2, 3, 4])
+def test_lp_centerpoint_has_centerpoint_depth(D):
+    """Algorithm 1's LP route: the point it returns for 16 points in R^D
+    lies in no open halfspace missing more than D/(D+1) of them, i.e. every
+    closed halfspace through it holds at least ceil(16/(D+1)) points
+    (checked over 20000 random directions)."""
+    import math
+    import numpy as np
+    from paper_2208_01498_amd.planner.ssa import centerpoint_lp
+    for seed in range(4):
+        rng = np.random.Generator(np.random.PCG64(900 + seed))
+        S = rng.standard_normal((16, D)) * np.array([1.0, 3.0, 0.2, 1.0][:D])
+        c = centerpoint_lp(S, rng, sample=16)
+        U = rng.standard_normal((20000, D))
+        U /= np.linalg.norm(U, axis=1, keepdims=True)
+        depth = int(((S - c) @ U.T >= -1e-12).sum(axis=0).min())
+        assert depth >= math.ceil(16 / (D + 1))
+
+
+def test_lp_centerpoint_plans_are_exact():
+    """A plan built with the LP centerpoint is the same contraction."""
+    circ = lattice_circuit(3, 4, 6, 910, "haar", "cz")
+    plan = make_plan(circ, n_slices=2, B=3, centerpoint="lp", bottom=8)
+    words = random_bitstrings(circ.n, 3, 911)
+    spec = plan.order_spec()
+    got = pairwise_amplitudes(circ, words, order=spec, sliced=spec["sliced"])
+    assert np.max(np.abs(got - statevector_amplitudes(circ, words))) <= 1e-12
