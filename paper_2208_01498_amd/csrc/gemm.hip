@@ -639,6 +639,13 @@ k_cgemm3m(GemmArgs g) {
     float* As = reinterpret_cast<float*>(smem);     // [2][3][KT][PA]
     float* Bs = As + 2 * 3 * KT * PA;               // [2][3][KT][PB]
     constexpr int QA = KT * PA, QB = KT * PB;       // plane strides
+    // Row k of a plane holds column x at x ^ sw(k), sw(k) = 16 ((k/2) mod 4)
+    // (mod the tile width): the four even rows that one store instruction
+    // writes when k is the contiguous global index (A untransposed, B
+    // transposed) then fall in four different bank groups instead of one,
+    // while a half-wave's 32 aligned columns stay 32 distinct banks
+    auto swa = [](int k) { return (((k >> 1) & 3) << 4) & (BM - 1); };
+    auto swb = [](int k) { return (((k >> 1) & 3) << 4) & (BN - 1); };
 
     auto store = [&](int buf) {
         float* a = As + buf * 3 * QA;
@@ -650,18 +657,19 @@ k_cgemm3m(GemmArgs g) {
             const float4 v = ra[i];
             if (TA) {
                 // (m, k), (m + 1, k): adjacent in every plane
-                const int k = f / (BM / 2), m = 2 * (f % (BM / 2));
+                const int k = f / (BM / 2), m = 2 * (f % (BM / 2)) ^ swa(k);
                 *reinterpret_cast<float2*>(a + k * PA + m) = make_float2(v.x, v.z);
                 *reinterpret_cast<float2*>(a + QA + k * PA + m) = make_float2(v.y, v.w);
                 *reinterpret_cast<float2*>(a + 2 * QA + k * PA + m) = make_float2(v.x + v.y, v.z + v.w);
             } else {
                 const int m = f / (KT / 2), k = 2 * (f % (KT / 2));
-                a[k * PA + m] = v.x;
-                a[QA + k * PA + m] = v.y;
-                a[2 * QA + k * PA + m] = v.x + v.y;
-                a[(k + 1) * PA + m] = v.z;
-                a[QA + (k + 1) * PA + m] = v.w;
-                a[2 * QA + (k + 1) * PA + m] = v.z + v.w;
+                const int m0s = m ^ swa(k), m1s = m ^ swa(k + 1);
+                a[k * PA + m0s] = v.x;
+                a[QA + k * PA + m0s] = v.y;
+                a[2 * QA + k * PA + m0s] = v.x + v.y;
+                a[(k + 1) * PA + m1s] = v.z;
+                a[QA + (k + 1) * PA + m1s] = v.w;
+                a[2 * QA + (k + 1) * PA + m1s] = v.z + v.w;
             }
         }
 #pragma unroll
@@ -670,18 +678,19 @@ k_cgemm3m(GemmArgs g) {
             if (f >= FB) break;
             const float4 v = rb[i];
             if (!TB) {
-                const int k = f / (BN / 2), n = 2 * (f % (BN / 2));
+                const int k = f / (BN / 2), n = 2 * (f % (BN / 2)) ^ swb(k);
                 *reinterpret_cast<float2*>(b + k * PB + n) = make_float2(v.x, v.z);
                 *reinterpret_cast<float2*>(b + QB + k * PB + n) = make_float2(v.y, v.w);
                 *reinterpret_cast<float2*>(b + 2 * QB + k * PB + n) = make_float2(v.x + v.y, v.z + v.w);
             } else {
                 const int n = f / (KT / 2), k = 2 * (f % (KT / 2));
-                b[k * PB + n] = v.x;
-                b[QB + k * PB + n] = v.y;
-                b[2 * QB + k * PB + n] = v.x + v.y;
-                b[(k + 1) * PB + n] = v.z;
-                b[QB + (k + 1) * PB + n] = v.w;
-                b[2 * QB + (k + 1) * PB + n] = v.z + v.w;
+                const int n0s = n ^ swb(k), n1s = n ^ swb(k + 1);
+                b[k * PB + n0s] = v.x;
+                b[QB + k * PB + n0s] = v.y;
+                b[2 * QB + k * PB + n0s] = v.x + v.y;
+                b[(k + 1) * PB + n1s] = v.z;
+                b[QB + (k + 1) * PB + n1s] = v.w;
+                b[2 * QB + (k + 1) * PB + n1s] = v.z + v.w;
             }
         }
     };
@@ -697,11 +706,11 @@ k_cgemm3m(GemmArgs g) {
 #pragma unroll
             for (int i = 0; i < WMF; ++i)
 #pragma unroll
-                for (int p = 0; p < 3; ++p) av[q][i][p] = a[p * QA + kr * PA + wm + i * 32 + l32];
+                for (int p = 0; p < 3; ++p) av[q][i][p] = a[p * QA + kr * PA + ((wm + i * 32 + l32) ^ swa(kr))];
 #pragma unroll
             for (int j = 0; j < WNF; ++j)
 #pragma unroll
-                for (int p = 0; p < 3; ++p) bv[q][j][p] = b[p * QB + kr * PB + wn + j * 32 + l32];
+                for (int p = 0; p < 3; ++p) bv[q][j][p] = b[p * QB + kr * PB + ((wn + j * 32 + l32) ^ swb(kr))];
         };
         rd(0, 0);
 #pragma unroll
