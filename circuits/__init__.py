@@ -21,7 +21,8 @@ from .families import (lattice_circuit, iqp_lattice_circuit, stack3d_circuit,
                        product_circuit, mirror, make_config, config_names,
                        random_bitstrings, pack_bits, unpack_bits,
                        circuit_seed, bitstring_seed, paper_iqp_circuit,
-                       sycamore_type_circuit, paper_family_instances)
+                       sycamore_type_circuit, paper_family_instances,
+                       sycamore_type_gate_counts, cavity_circuit_gate_counts)
 
 __all__ = [
     "H", "SQRT_X", "SQRT_Y", "SQRT_W", "CZ", "z_phase", "cphase", "fsim",
@@ -29,5 +30,6 @@ __all__ = [
     "iqp_lattice_circuit", "stack3d_circuit", "product_circuit", "mirror",
     "make_config", "config_names", "random_bitstrings", "pack_bits",
     "unpack_bits", "circuit_seed", "bitstring_seed", "paper_iqp_circuit",
-    "sycamore_type_circuit", "paper_family_instances",
+    "sycamore_type_circuit", "paper_family_instances", "sycamore_type_gate_counts",
+    "cavity_circuit_gate_counts",
 ]

@@ -183,6 +183,83 @@ def paper_family_instances(L):
             ("sycamore_type_q=5_p=0.5", sycamore_type_circuit(L, 5, 0.5, 5400 + L), 40)]
 
 
+def _pattern_counts(free, pat):
+    """Two-qubit gates per site of an L x L grid for edge pattern `pat`
+    (P0/P2: horizontal pairs from even/odd columns, P1/P3: vertical pairs
+    from even/odd rows), a gate on a pair when both sites are free."""
+    L = free.shape[-1]
+    f = np.zeros(free.shape, dtype=np.int64)
+    start = 0 if pat in (0, 1) else 1
+    idx = np.arange(start, L - 1, 2)
+    if pat in (0, 2):
+        g = free[..., :, idx] & free[..., :, idx + 1]
+        f[..., :, idx] += g
+        f[..., :, idx + 1] += g
+    else:
+        g = free[..., idx, :] & free[..., idx + 1, :]
+        f[..., idx, :] += g
+        f[..., idx + 1, :] += g
+    return f
+
+
+def sycamore_type_gate_counts(L, periods, p_inaccessible, seed):
+    """Two-qubit gate count per qubit (L x L array) of a Sycamore-type
+    circuit under the rule of `sycamore_type_circuit` (each edge pattern
+    twice per period, a qubit inaccessible for a whole period with
+    probability p), without building the gates: for the bound evaluations
+    at sizes whose gate lists would not fit in memory.  One realization per
+    seed (its own random stream, not that of `sycamore_type_circuit`)."""
+    rng = _rng(seed)
+    f = np.zeros((L, L), dtype=np.int64)
+    for _ in range(periods):
+        free = rng.random((L, L)) >= p_inaccessible
+        for pat in range(4):
+            f += 2 * _pattern_counts(free, pat)
+    return f
+
+
+def cavity_circuit_gate_counts(L, seed, alpha=0.1, S=5, sigma=10.0, lam=None):
+    """The paper's third example, (2+1)-dimensional random circuits with
+    cavities, as two-qubit gate counts per qubit (L x L) and the number of
+    time steps T = max(1, round(alpha L)).  Each time step applies one edge
+    pattern of uniformly random orientation and parity (a dense layer of
+    nearest-neighbour gates) to the pairs whose sites are both outside every
+    cavity; v ~ Poisson(lam) cavities of S x S x S space-time sites have
+    uniformly random corners, and each is kept with probability
+    exp(-(x^2/L^2 + y^2/L^2 + t^2/T^2) / sigma^2), with (x, y, t) its centre
+    measured from the centre of the circuit's space-time box.
+    lam = 5e4 (L/200)^3.5 by default."""
+    rng = _rng(seed)
+    T = max(1, int(round(alpha * L)))
+    if lam is None:
+        lam = 5e4 * (L / 200.0) ** 3.5
+    v = int(rng.poisson(lam))
+    corner = np.stack([rng.integers(0, T, v), rng.integers(0, L, v), rng.integers(0, L, v)], axis=1)
+    ctr = corner + (S - 1) / 2.0 - np.array([T, L, L]) / 2.0
+    keep = rng.random(v) < np.exp(-((ctr[:, 1] / L) ** 2 + (ctr[:, 2] / L) ** 2 +
+                                    (ctr[:, 0] / T) ** 2) / sigma ** 2)
+    corner = corner[keep]
+    # coverage by a 3-D difference array: +1 at a box's low corner, signed
+    # corrections at the other seven corners, then prefix sums
+    diff = np.zeros((T + 1, L + 1, L + 1), dtype=np.int32)
+    hi = np.minimum(corner + S, np.array([T, L, L]))
+    for dt in (0, 1):
+        for dx in (0, 1):
+            for dy in (0, 1):
+                sign = (-1) ** (dt + dx + dy)
+                pt = np.where(dt, hi[:, 0], corner[:, 0])
+                px = np.where(dx, hi[:, 1], corner[:, 1])
+                py = np.where(dy, hi[:, 2], corner[:, 2])
+                np.add.at(diff, (pt, px, py), sign)
+    cover = diff.cumsum(0).cumsum(1).cumsum(2)[:T, :L, :L]
+    free = cover == 0
+    pats = rng.integers(0, 4, T)
+    f = np.zeros((L, L), dtype=np.int64)
+    for t in range(T):
+        f += _pattern_counts(free[t], int(pats[t]))
+    return f, T
+
+
 def stack3d_circuit(X, Y, Z, layers, seed, name=""):
     """(2+1)-dimensional-style random circuit on an X x Y x Z qubit stack
     (q = x + X*y + X*Y*z).  Each layer picks an axis uniformly from {x,y,z}

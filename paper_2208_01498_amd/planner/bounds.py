@@ -21,7 +21,10 @@ Reading of the planar d = 2 statement: the proof puts identity tensors of
 M = 4^4 entries at line crossings, which makes the exponent 8 a_2' sqrt(n')
 with n' = sum_i f_i (2 + f_i / 2); the statement of Theorem 2 prints 4 a_2'.
 `theorem2_planar_log2` takes log2 M as an argument (8 by default, the
-proof's M; 4 reproduces the printed exponent).
+proof's M; 4 reproduces the printed exponent).  The paper's reported
+crossovers (planar bound against side-wise contraction and explicit
+evolution for its cavity and Sycamore-type families) come out with the
+proof's M and not with the printed exponent.
 """
 import math
 

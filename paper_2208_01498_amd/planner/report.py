@@ -41,12 +41,75 @@ def family_rows(Ls=(4, 5, 6, 7, 8), doubled=True):
     return rows
 
 
+def large_size_rows(kind, L, reps=10):
+    """Bounds only, at the paper's large sizes, from two-qubit gate counts
+    (no gate list): `kind` "sycamore" (5 periods, p = 0.88, T = 40 cycles)
+    or "cavity" ((2+1)-D with cavities, T = round(0.1 L)).  Per realization:
+    log2 of Theorem 2 (general and planar d = 2 forms), side-wise and
+    explicit evolution; returns the list of dicts."""
+    import numpy as np
+    from circuits import sycamore_type_gate_counts, cavity_circuit_gate_counts
+    from .bounds import (theorem2_log2, theorem2_planar_log2, sidewise_log2, explicit_log2)
+    rows = []
+    for r in range(reps):
+        if kind == "sycamore":
+            f = sycamore_type_gate_counts(L, 5, 0.88, 7000 + 31 * L + r)
+            T = 40
+        else:
+            f, T = cavity_circuit_gate_counts(L, 8000 + 31 * L + r)
+        f = f.ravel()
+        act = f[f > 0]
+        rows.append({"L": L, "T": T, "idle": int((f == 0).sum()), "F": int(f.max()),
+                     "log2_theorem2": theorem2_log2(act, 2, 1.0),
+                     "log2_theorem2_planar": theorem2_planar_log2(act),
+                     "log2_sidewise": sidewise_log2(int(f.max()), L, 2),
+                     "log2_explicit": explicit_log2(T, L * L, int((f == 0).sum()))})
+    return rows
+
+
+def crossover_table(kind, Ls, reps=10):
+    """Mean log2 of each bound and the fraction of realizations in which the
+    planar Theorem 2 bound beats side-wise contraction, explicit evolution,
+    and both."""
+    import numpy as np
+    out = []
+    for L in Ls:
+        rs = large_size_rows(kind, L, reps)
+        mean = lambda k: float(np.mean([r[k] for r in rs]))
+        out.append({"family": kind, "L": L, "reps": reps,
+                    "log2_theorem2": mean("log2_theorem2"),
+                    "log2_theorem2_planar": mean("log2_theorem2_planar"),
+                    "log2_sidewise": mean("log2_sidewise"), "log2_explicit": mean("log2_explicit"),
+                    "frac_below_sidewise": float(np.mean([r["log2_theorem2_planar"] < r["log2_sidewise"] for r in rs])),
+                    "frac_below_explicit": float(np.mean([r["log2_theorem2_planar"] < r["log2_explicit"] for r in rs])),
+                    "frac_below_both": float(np.mean([r["log2_theorem2_planar"] < min(r["log2_sidewise"], r["log2_explicit"]) for r in rs]))})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--L", type=int, nargs="+", default=[4, 5, 6, 7, 8])
     ap.add_argument("--no-doubled", action="store_true")
     ap.add_argument("--json", action="store_true")
+    ap.add_argument("--large", action="store_true",
+                    help="bounds only at the paper's large sizes (Sycamore-type L = 200..1600, "
+                         "cavity circuits L = 150..300)")
     args = ap.parse_args()
+    if args.large:
+        rows = (crossover_table("sycamore", (200, 400, 800, 1600))
+                + crossover_table("cavity", (150, 200, 250, 300)))
+        if args.json:
+            print(json.dumps(rows))
+            return
+        cols = ["family", "L", "log2_theorem2", "log2_theorem2_planar", "log2_sidewise",
+                "log2_explicit", "frac_below_sidewise", "frac_below_explicit", "frac_below_both"]
+        print("| " + " | ".join(cols) + " |")
+        print("|" + "---|" * len(cols))
+        for r in rows:
+            print("| " + " | ".join(("%.0f" % r[c]) if c.startswith("log2") else
+                                    ("%.1f" % r[c]) if c.startswith("frac") else str(r[c])
+                                    for c in cols) + " |", flush=True)
+        return
     rows = family_rows(args.L, doubled=not args.no_doubled)
     if args.json:
         print(json.dumps(rows))
