@@ -37,10 +37,10 @@ EXEC = {"fp32": 1.0, "fp32_3m": 0.75, "bf16x3": 3.0, "fp16x3": 3.0, "bf16x1": 1.
 # changed kernel or plan reports null until it is measured again.
 TRAFFIC = [
     {"class": "cgemm_mfma_128x128", "precision": "fp32_3m", "source": "gemm.hip",
-     "source_sha256": "c905be7704091c690afd51e9dfa36b82846d35373437a68ffcab70a4f8a318d0",
+     "source_sha256": "33eae762e86f35d82c1280114aae6eff2057410d15585082ed28e4025bdb94b6",
      "chunk": 30, "flops_per_amplitude": 40093516002040.0,
-     "bytes_per_launch": 1.386e11,
-     "note": "HBM fetch 1.289e11 + write 9.700e9 bytes per launch (the 156 launches of one "
+     "bytes_per_launch": 1.420e11,
+     "note": "HBM fetch 1.323e11 + write 9.700e9 bytes per launch (the 156 launches of one "
              "timed step; FETCH_SIZE x2.0 and WRITE_SIZE x1.0 from a 1 GiB copy); algorithmic "
              "1.646e10"},
 ]

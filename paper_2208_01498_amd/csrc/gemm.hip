@@ -28,8 +28,8 @@
 //                   K is cut into a fixed number of ranges whose partial
 //                   products are summed in range order by k_reduce_splitk
 // Tiles: WGM x WGN waves per workgroup (4 or 8); a wave owns WMF x WNF
-// blocks of 32 x 16 (4M, split) or 32 x 32 (3M) complex outputs; 8 (FP32) or
-// 16 (split) complex k per stage; global loads of the next stage are issued
+// blocks of 32 x 16 (4M, split) or 32 x 32 (3M) complex outputs; 8 complex k
+// per stage; global loads of the next stage are issued
 // before the MFMAs of the current one and land in the other half of a
 // double-buffered LDS, one barrier per stage.
 #include <hip/hip_runtime.h>
@@ -46,7 +46,8 @@ typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
-constexpr int KT_SPLIT = 16;   // complex k per LDS stage, split bf16 (two MFMA k-steps)
+constexpr int KT_SPLIT = 8;    // complex k per LDS stage, split modes (one MFMA k-step; keeps
+                               // two workgroups per CU)
 constexpr int KT_FP32 = 8;     // complex k per LDS stage, FP32 (keeps two workgroups per CU)
 constexpr int KT = 16;         // K granularity of the split-K ranges
 
@@ -461,7 +462,18 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
     RowDep rd;
     if (fastdep) rd.init(g.cPM);
 #pragma unroll
-    for (int i = 0; i < WMF; ++i)
+    for (int i = 0; i < WMF; ++i) {
+        // split fp16: the inverse scales of this lane's 16 rows, shared by
+        // all column blocks
+        float urow[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            urow[r] = 1.f;
+            if constexpr (PREC == 3) {
+                const int mp = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (mp < Mt) urow[r] = exp2i(-scale_exp(g.xA[operand_copy(g, 0, bb, ib, rr) * Mt + mp]));
+            }
+        }
 #pragma unroll
         for (int j = 0; j < WNF; ++j) {
             const int np = n0 + wn + j * 16 + (l32 >> 1);
@@ -487,11 +499,11 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
                         (fastdep ? (size_t)(dbase | rd.low(r, half)) : gemm_c_elem(g, m, n));
                 }
                 float v = acc[i][j][r];
-                if constexpr (PREC == 3)
-                    v = (v * ucol) * exp2i(-scale_exp(g.xA[operand_copy(g, 0, bb, ib, rr) * Mt + mp]));
+                if constexpr (PREC == 3) v = (v * ucol) * urow[r];
                 reinterpret_cast<float*>(Cb + e)[l32 & 1] = v;
             }
         }
+    }
 }
 
 // ---------------------------------------------------------------------------
