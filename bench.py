@@ -253,6 +253,10 @@ def main():
     ap.add_argument("--width", type=float, default=None)
     ap.add_argument("--arena-gb", type=float, default=None)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-after", action="store_true",
+                    help="time the steps without per-launch events (captured HIP graphs replay), "
+                         "then run one more step with events for the per-kernel figures: for "
+                         "launch-bound workloads")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--serve", action="store_true", help="served mixed stream instead")
@@ -303,8 +307,10 @@ def main():
         eng.amplitudes(p, words, prec)
         log("warmup step done", B.tn_last_exec_stats(eng.ctx)["chunk"])
     # per-kernel HIP events on the executing stream, recorded inside the
-    # timed region (read back only every few thousand launches)
-    B.tn_ctx_set_profiling(eng.ctx, 1)
+    # timed region (read back only every few thousand launches); with
+    # --profile-after the timed steps run without them and one more step
+    # records them
+    B.tn_ctx_set_profiling(eng.ctx, 0 if args.profile_after else 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -312,6 +318,11 @@ def main():
         log("timed step %d done" % k)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    graph_replays = B.tn_last_exec_stats(eng.ctx)["graph_replays"]
+    if args.profile_after:
+        B.tn_ctx_set_profiling(eng.ctx, 1)
+        eng.amplitudes(p, words, prec)
+        torch.cuda.synchronize()
     B.tn_ctx_set_profiling(eng.ctx, 0)
     st = B.tn_last_exec_stats(eng.ctx)
     el = t1 - t0
@@ -366,6 +377,9 @@ def main():
                    "slices": 1 << len(plan.sliced), "precision": args.precision,
                    "chunk": st["chunk"], "n_chunks": st["n_chunks"],
                    "slice_block": st["slice_block"],
+                   "timing": ("steps without per-launch events (graph replays in the last: %d), "
+                              "kernel figures from one more step with events" % graph_replays)
+                   if args.profile_after else "per-launch events inside the timed steps",
                    "algorithmic_flops_per_amplitude": st["algorithmic_flops"] / nb},
         "roofline": roofline,
         "achieved_algorithmic_tflops": st["algorithmic_flops"] * args.steps / el / 1e12,

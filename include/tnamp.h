@@ -185,7 +185,7 @@ typedef struct tn_exec_stats {
     int32_t chunk;                    /* bitstrings per device chunk */
     int32_t n_chunks;
     int32_t slice_block;              /* slices computed together per pass */
-    int32_t reserved;
+    int32_t graph_replays;            /* chunks run by replaying a captured HIP graph */
     double algorithmic_flops;         /* sum over executed steps     */
     double permute_bytes;             /* 16 bytes per permuted element */
     /* per kernel class (0 dot-product GEMM for tiny outputs, 1 MFMA GEMM
@@ -201,8 +201,20 @@ typedef struct tn_exec_stats {
     double bytes[6];
 } tn_exec_stats;
 
-/* Turn per-launch event timing of tn_contract_amplitudes on (1) or off (0). */
+/* Turn per-launch event timing of tn_contract_amplitudes on (1) or off (0).
+ * While it is on, chunks are launched kernel by kernel (no graph replay). */
 int tn_ctx_set_profiling(tn_ctx* ctx, int32_t on);
+
+/* HIP graphs for repeated calls (default on).  The kernels of one chunk
+ * (accumulator reset, every gather, permute and GEMM of every pass, slice
+ * sums and final scale) depend only on the plan, the chunk size, the slice
+ * block, the precision and the workspace address; the bitstrings are read
+ * from device memory that each call refills before the launch.  The second
+ * time such a chunk runs it is captured into a graph, and later runs replay
+ * it with one launch.  Graphs of a plan are destroyed when it is unloaded;
+ * at most 256 are kept per context.  Results are bitwise the same either
+ * way. */
+int tn_ctx_set_graphs(tn_ctx* ctx, int32_t on);
 
 /* Slices computed together per pass of the slice loop, as log2 (-1 =
  * automatic: the largest block that fits the workspace).  Tensors that depend

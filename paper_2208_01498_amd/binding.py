@@ -22,7 +22,7 @@ PRECISIONS = {"fp32": TN_FP32_4M, "fp32_3m": TN_FP32_3M, "bf16x3": TN_SPLIT_BF16
 EXPORTED = ["tn_ctx_create", "tn_ctx_destroy", "tn_plan_load", "tn_plan_validate",
             "tn_plan_info", "tn_plan_unload", "tn_contract_amplitudes", "tn_submit",
             "tn_poll", "tn_cancel", "tn_server_config", "tn_server_set_heavy", "tn_server_stop",
-            "tn_last_exec_stats", "tn_ctx_set_profiling", "tn_ctx_set_slice_block", "tn_kernel_cgemm", "tn_kernel_cgemm_scratch_bytes", "tn_kernel_permute",
+            "tn_last_exec_stats", "tn_ctx_set_profiling", "tn_ctx_set_slice_block", "tn_ctx_set_graphs", "tn_kernel_cgemm", "tn_kernel_cgemm_scratch_bytes", "tn_kernel_permute",
             "tn_last_error"]
 
 
@@ -52,7 +52,7 @@ class tn_exec_stats(ctypes.Structure):
                 ("kernels_gather", ctypes.c_int64), ("steps_executed", ctypes.c_int64),
                 ("steps_reused", ctypes.c_int64), ("chunk", ctypes.c_int32),
                 ("n_chunks", ctypes.c_int32), ("slice_block", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("algorithmic_flops", ctypes.c_double),
+                ("graph_replays", ctypes.c_int32), ("algorithmic_flops", ctypes.c_double),
                 ("permute_bytes", ctypes.c_double), ("launches", ctypes.c_int64 * 6),
                 ("time_ms", ctypes.c_double * 6), ("flops", ctypes.c_double * 6),
                 ("bytes", ctypes.c_double * 6)]
@@ -91,6 +91,7 @@ def load_library(path=LIB_PATH):
         "tn_last_exec_stats": [vp, ctypes.POINTER(tn_exec_stats)],
         "tn_ctx_set_profiling": [vp, i32],
         "tn_ctx_set_slice_block": [vp, i32],
+        "tn_ctx_set_graphs": [vp, i32],
         "tn_kernel_cgemm": [vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, ctypes.c_int64,
                             ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                             ctypes.c_int64, i32, vp, sz, vp],
@@ -230,6 +231,10 @@ def tn_last_exec_stats(ctx):
 
 def tn_ctx_set_slice_block(ctx, log2_block):
     _check(load_library().tn_ctx_set_slice_block(ctx, log2_block))
+
+
+def tn_ctx_set_graphs(ctx, on):
+    _check(load_library().tn_ctx_set_graphs(ctx, 1 if on else 0))
 
 
 def tn_ctx_set_profiling(ctx, on):

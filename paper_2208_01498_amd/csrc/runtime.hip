@@ -99,6 +99,106 @@ bool choose_shape(const tn_plan* plan, int nb, size_t ws_bytes, int force_r, int
     return true;
 }
 
+static void add_stats(tn_exec_stats& a, const tn_exec_stats& d, int sign) {
+    a.kernels_gemm += sign * d.kernels_gemm;
+    a.kernels_permute += sign * d.kernels_permute;
+    a.kernels_gather += sign * d.kernels_gather;
+    a.steps_executed += sign * d.steps_executed;
+    a.steps_reused += sign * d.steps_reused;
+    a.algorithmic_flops += sign * d.algorithmic_flops;
+    a.permute_bytes += sign * d.permute_bytes;
+    for (int i = 0; i < 6; ++i) {
+        a.launches[i] += sign * d.launches[i];
+        a.flops[i] += sign * d.flops[i];
+        a.bytes[i] += sign * d.bytes[i];
+    }
+}
+
+// Run the kernels of one chunk: directly the first time a (plan, workspace,
+// chunk, slice block, precision) shape is seen, captured into a HIP graph
+// the second time, replayed with one launch after that.  Graphs are off
+// while per-launch events are recorded, and once a context holds
+// kMaxGraphs of them.
+static constexpr size_t kMaxGraphs = 256;
+
+template <class F>
+static int run_chunk(tn_ctx* ctx, const tn_plan* plan, const char* ws, int cb, int r, int precision,
+                     hipStream_t stream, bool graphable, tn_exec_stats& es, F&& launches) {
+    graphable = graphable && ctx && ctx->use_graphs;
+    hipGraphExec_t replay = nullptr;
+    tn_exec_stats delta{};
+    bool capture = false;
+    const auto key = std::make_tuple(plan, ws, cb, r, precision);
+    if (graphable) {
+        std::lock_guard<std::mutex> g(ctx->gmu);
+        auto it = ctx->graphs.find(key);
+        if (it == ctx->graphs.end()) {
+            if (ctx->graphs.size() < kMaxGraphs) ctx->graphs[key].stamp = ++ctx->graph_clock;
+        } else if (it->second.exec) {
+            replay = it->second.exec;
+            delta = it->second.delta;
+        } else {
+            capture = true;
+        }
+    }
+    if (replay) {
+        HIPCHK(ctx, hipGraphLaunch(replay, stream));
+        add_stats(es, delta, 1);
+        es.graph_replays++;
+        return TN_OK;
+    }
+    if (!capture) return launches();
+    const tn_exec_stats before = es;
+    HIPCHK(ctx, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    const int rc = launches();
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(stream, &graph);
+    if (rc || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc) return rc;
+        set_error(std::string("HIP error: ") + hipGetErrorString(e) + " at hipStreamEndCapture");
+        ctx->poisoned = true;
+        return TN_EDEVICE;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        set_error(std::string("HIP error: ") + hipGetErrorString(ei) + " at hipGraphInstantiate");
+        ctx->poisoned = true;
+        return TN_EDEVICE;
+    }
+    delta = es;
+    add_stats(delta, before, -1);
+    {
+        std::lock_guard<std::mutex> g(ctx->gmu);
+        auto& ent = ctx->graphs[key];
+        if (ent.exec) {
+            // captured meanwhile by another call of the same shape: keep that one
+            (void)hipGraphExecDestroy(exec);
+            exec = ent.exec;
+        } else {
+            ent.exec = exec;
+            ent.delta = delta;
+        }
+    }
+    HIPCHK(ctx, hipGraphLaunch(exec, stream));
+    return TN_OK;
+}
+
+// drop the graphs of one plan (all plans when plan is null)
+void drop_graphs(tn_ctx* ctx, const tn_plan* plan) {
+    std::lock_guard<std::mutex> g(ctx->gmu);
+    for (auto it = ctx->graphs.begin(); it != ctx->graphs.end();) {
+        if (!plan || std::get<0>(it->first) == plan) {
+            if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+            it = ctx->graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
 int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int precision,
             hipStream_t stream, char* ws, size_t ws_bytes, double* out, tn_exec_stats* stats,
             int shape_r, int shape_chunk) {
@@ -166,6 +266,9 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
         uint64_t* d_bits = reinterpret_cast<uint64_t*>(ws + mp.bits_off);
         double2* d_acc = reinterpret_cast<double2*>(ws + mp.acc_off);
         HIPCHK(ctx, hipMemcpyAsync(d_bits, bits + c0, sizeof(uint64_t) * cb, hipMemcpyHostToDevice, stream));
+        // every kernel of the chunk: the same launches, with the same
+        // arguments, for any call with this plan, workspace and shape
+        auto launches = [&]() -> int {
         HIPCHK(ctx, launch_zero_acc(d_acc, cb, stream));
         // tensor layout in the workspace: [copy][bitstring][labels], one copy
         // per value of the low slice bits the tensor depends on
@@ -322,6 +425,10 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
                                           ncopy(root), per_r(root), stream));
         }
         HIPCHK(ctx, launch_finalize(d_acc, cb, p.scale.real(), p.scale.imag(), stream));
+        return TN_OK;
+        };
+        int rcc = run_chunk(ctx, plan, ws, cb, r, precision, stream, !prof, es, launches);
+        if (rcc) return rcc;
         HIPCHK(ctx, hipMemcpyAsync(out + 2 * (size_t)c0, d_acc, sizeof(double2) * cb, hipMemcpyDeviceToHost, stream));
         HIPCHK(ctx, hipStreamSynchronize(stream));
         int rch = harvest();
@@ -379,6 +486,7 @@ int tn_ctx_destroy(tn_ctx* ctx) {
     tn_server_stop(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    drop_graphs(ctx, nullptr);
     (void)hipStreamDestroy(ctx->stream);
     for (auto e : ctx->events) (void)hipEventDestroy(e);
     for (tn_plan* p : ctx->plans) {      // plans still loaded
@@ -454,6 +562,7 @@ int tn_plan_unload(tn_ctx* ctx, tn_plan* plan) {
         ctx->plans.erase(plan);
     }
     (void)hipSetDevice(ctx->device);
+    drop_graphs(ctx, plan);
     (void)hipFree(plan->d_leaves);
     delete plan;
     return TN_OK;
@@ -568,6 +677,12 @@ int tn_kernel_permute(const void* src, void* dst, int32_t rank, const int32_t* p
 int tn_ctx_set_profiling(tn_ctx* ctx, int32_t on) {
     if (!ctx) return TN_EINVAL;
     ctx->profile = on != 0;
+    return TN_OK;
+}
+
+int tn_ctx_set_graphs(tn_ctx* ctx, int32_t on) {
+    if (!ctx) { set_error("null argument"); return TN_EINVAL; }
+    ctx->use_graphs = on != 0;
     return TN_OK;
 }
 

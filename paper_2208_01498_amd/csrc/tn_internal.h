@@ -13,6 +13,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -192,6 +193,17 @@ struct tn_ctx {
     std::vector<hipEvent_t> events;
     std::set<tn_plan*> plans;            // loaded and not yet unloaded (guarded by smu)
     int force_slice_block = -1;          // log2 slices per pass, -1 = automatic
+    // captured chunks: (plan, workspace, chunk, slice-block bits, precision)
+    // -> graph and the launch statistics it stands for (guarded by gmu)
+    bool use_graphs = true;
+    std::mutex gmu;
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;   // null: seen once, not captured yet
+        tn_exec_stats delta{};
+        uint64_t stamp = 0;
+    };
+    std::map<std::tuple<const tn_plan*, const char*, int, int, int>, GraphEntry> graphs;
+    uint64_t graph_clock = 0;
 };
 
 namespace tn {
@@ -200,6 +212,8 @@ namespace tn {
 int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb,
             int precision, hipStream_t stream, char* ws, size_t ws_bytes,
             double* out, tn_exec_stats* stats, int shape_r = 0, int shape_chunk = 0);
+// destroy the captured graphs of a plan (of every plan when plan is null)
+void drop_graphs(tn_ctx* ctx, const tn_plan* plan);
 // execution shape (log2 slices per pass, bitstrings per pass) for a workspace
 bool choose_shape(const tn_plan* plan, int nb, size_t ws_bytes, int force_r, int& r, int& chunk,
                   bool scales = false);
