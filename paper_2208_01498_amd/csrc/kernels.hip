@@ -91,6 +91,42 @@ __global__ void __launch_bounds__(256) k_permute_tiled(PermArgs a) {
             e_lo |= 1u << a.t_rank[m + 1];
         }
     const unsigned e_bit0 = 1u << a.t_rank[0];    // input tile index of output bit 0
+    if (tp - tl <= 3) {
+        // tiles of at most 2^12 elements (the size the host picks): a
+        // thread's at most 8 pairs have their high index bits in three
+        // masks, all 8 reads are issued before the first LDS write, and the
+        // reads and writes beyond the tile (pair index >= iters) repeat pair
+        // 0 into LDS rows past the tile (the LDS holds 2^12 elements)
+        size_t hin[3] = {0, 0, 0}, hout[3] = {0, 0, 0};
+        unsigned he[3] = {0, 0, 0};
+        for (int j = 0; j < tp - tl; ++j) {
+            hin[j] = size_t(1) << a.t_in[tl + 1 + j];
+            hout[j] = size_t(1) << a.t_out[tl + 1 + j];
+            he[j] = 1u << a.t_rank[tl + 1 + j];
+        }
+        float4 v[8];
+#pragma unroll
+        for (unsigned k = 0; k < 8; ++k) {
+            const unsigned kk = k < iters ? k : 0u;
+            const size_t off = in_lo | ((kk & 1) ? hin[0] : 0) | ((kk & 2) ? hin[1] : 0) |
+                               ((kk & 4) ? hin[2] : 0);
+            v[k] = *reinterpret_cast<const float4*>(src + off);
+        }
+#pragma unroll
+        for (unsigned k = 0; k < 8; ++k)
+            *reinterpret_cast<float4*>(&lds[swz((((k << tl) | th) << 1))]) = v[k];
+        __syncthreads();
+#pragma unroll
+        for (unsigned k = 0; k < 8; ++k) {
+            if (k >= iters) break;
+            const size_t off = out_lo | ((k & 1) ? hout[0] : 0) | ((k & 2) ? hout[1] : 0) |
+                               ((k & 4) ? hout[2] : 0);
+            const unsigned e = e_lo | ((k & 1) ? he[0] : 0) | ((k & 2) ? he[1] : 0) | ((k & 4) ? he[2] : 0);
+            const float2 x = lds[swz(e)], y = lds[swz(e | e_bit0)];
+            *reinterpret_cast<float4*>(dst + off) = make_float4(x.x, x.y, y.x, y.y);
+        }
+        return;
+    }
     for (unsigned k = 0; k < iters; ++k) {
         size_t off = in_lo;
         for (int m = tl; m < tp; ++m)
@@ -154,8 +190,10 @@ hipError_t launch_gather(const GatherArgs& g, hipStream_t s) {
 hipError_t launch_permute(const PermArgs& a, hipStream_t s) {
     size_t tiles = size_t(1) << a.nn;
     size_t tile_elems = size_t(1) << a.nt;
-    // the swizzle moves an index within its 1024-element block
-    size_t lds = (tile_elems < 1024 ? 1024 : tile_elems) * sizeof(float2);
+    // the swizzle moves an index within its 1024-element block; tiles up to
+    // 2^12 elements get the whole 2^12 (their eight-pair path writes past a
+    // smaller tile)
+    size_t lds = (tile_elems < 4096 ? 4096 : tile_elems) * sizeof(float2);
     int threads = tile_elems >= 512 ? 256 : (int)((tile_elems / 2 + 63) / 64 * 64);
     if (threads < 64) threads = 64;
     hipLaunchKernelGGL(k_permute_tiled, dim3((unsigned)tiles, (unsigned)a.nb), dim3(threads), lds, s, a);
