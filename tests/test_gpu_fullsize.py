@@ -181,3 +181,53 @@ def test_plain_bf16_rounding_is_the_weaker_reference(eng):
     assert e1 > e3
     # 11-bit halves carry more of each operand than 8-bit ones
     assert e16 <= e3
+
+
+
+@functools.lru_cache(maxsize=None)
+def _stored(name):
+    """Bitstrings, stored oracle amplitudes and the plan blob for `name`."""
+    import json
+    import os
+    from paper_2208_01498_amd.planner.plan import make_plan
+    path = os.path.join(os.path.dirname(__file__), "golden", "fullsize_oracle_amplitudes.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    if name not in data:
+        return None
+    rows = data[name]["amplitudes"]
+    words = np.array([int(r["bitstring"]) for r in rows], dtype=np.uint64)
+    ref = np.array([complex(r["re"], r["im"]) for r in rows])
+    circ, _, _ = make_config(name)
+    if name == "cfg3":
+        plan = _plan(circ, 10, len(words))              # the timed plan shape, 2^10 slices
+    else:
+        plan = make_plan(circ, n_slices=None, target_width=28, B=len(words), trials=1)
+        assert plan.stats["max_bits"] <= 28
+    return circ, words, ref, plan.to_blob()
+
+
+def _check_stored(eng, name, prec):
+    got = _stored(name)
+    if got is None:
+        pytest.skip("no stored oracle amplitudes for " + name)
+    circ, words, ref, blob = got
+    print("case %s stored oracle, %d bitstrings, prec %d" % (name, len(words), prec), flush=True)
+    a = eng.amplitudes(eng.load(blob), words, prec)
+    err = (np.abs(a - ref) / np.maximum(np.abs(ref), 2.0 ** (-circ.n / 2))).max()
+    print("max err", err, "max plain relative", (np.abs(a - ref) / np.abs(ref)).max(), flush=True)
+    assert err <= (1e-3 if prec in (2, 3) else 1e-5)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_headline_vs_stored_oracle(eng, prec):
+    """The 8x8 depth-16 workload at its full size, in the timed plan shape
+    (2^10 slices), against complex128 oracle amplitudes of its first
+    bitstrings with every slice summed (stored by the golden script)."""
+    _check_stored(eng, "cfg3", prec)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_fsim_6x6_depth12_vs_stored_oracle(eng, prec):
+    """The 6x6 depth-12 fSim workload at its full size (per-slice rank at
+    most 28) against stored complex128 oracle amplitudes."""
+    _check_stored(eng, "cfg2", prec)
