@@ -199,11 +199,16 @@ def ssa_candidates(pts, radii, rng, n_circles=24, method="radon"):
     alpha = np.sqrt((1 - nc) / (1 + nc))                     # step 4
     yr = y @ R.T
     # choose the dilation direction that centres the points (the map moves
-    # the point (0,..,0,|c|) to the origin for one of alpha, 1/alpha)
+    # the point (0,..,0,|c|) to the origin for one of alpha, 1/alpha).  A
+    # centerpoint on a data point that several factors share (coincident
+    # positions) puts those points on the pole, where the map is undefined:
+    # they are left out of the score
     best = None
     for a in (alpha, 1.0 / alpha):
-        z = _dilate(yr, a)
-        score = np.linalg.norm(z.mean(axis=0))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            z = _dilate(yr, a)
+        z = z[np.all(np.isfinite(z), axis=1)]
+        score = np.linalg.norm(z.mean(axis=0)) if len(z) else np.inf
         if best is None or score < best[0]:
             best = (score, a)
     a = best[1]

@@ -356,3 +356,30 @@ def test_lp_centerpoint_plans_are_exact():
     spec = plan.order_spec()
     got = pairwise_amplitudes(circ, words, order=spec, sliced=spec["sliced"])
     assert np.max(np.abs(got - statevector_amplitudes(circ, words))) <= 1e-12
+
+
+
+
+def test_ssa_candidates_with_centerpoint_on_a_shared_point():
+    """Coincident factor positions (here 40 of 64 points at the mean, the
+    rest in symmetric pairs) put the LP centerpoint on the shared point,
+    which the rotation sends to the pole where the dilation is undefined:
+    the candidates still come out finite, with no division warning."""
+    import warnings
+    g = np.random.Generator(np.random.PCG64(5))
+    half = g.standard_normal((12, 2)) * 2.0
+    pts = np.vstack([np.zeros((40, 2)), half, -half])
+    radii = np.full(len(pts), 0.26)
+    # the case is reached: the centerpoint of the projected points is the
+    # image of the shared point, the south pole of S^2
+    mu = pts.mean(axis=0)
+    y = ssa.stereo((pts - mu) / np.max(np.linalg.norm(pts - mu, axis=1)))
+    c = ssa.centerpoint_lp(y, np.random.Generator(np.random.PCG64(900)))
+    assert np.linalg.norm(c - np.array([0.0, 0.0, -1.0])) < 1e-9
+    with warnings.catch_warnings():
+        warnings.simplefilter("error", RuntimeWarning)
+        seps = ssa.ssa_candidates(pts, radii, np.random.Generator(np.random.PCG64(900)),
+                                  n_circles=24, method="lp")
+    assert seps
+    for kind, a, b in seps:
+        assert np.all(np.isfinite(a)) and np.isfinite(b)
