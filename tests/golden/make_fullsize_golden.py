@@ -6,10 +6,14 @@ come from a plan used as data (the oracle's own greedy order would not fit
 in host memory at these sizes); they change the result only at rounding
 level.  Run from the repository root:
 
-    python tests/golden/make_fullsize_golden.py [cfg3|cfg2 ...]
+    python tests/golden/make_fullsize_golden.py [--meta-only] [cfg3|cfg2 ...]
 
-It takes tens of minutes per amplitude on a few cores.
+It takes about ten minutes per 8x8 amplitude on a few cores.  Each entry
+also records the bitstrings and a SHA-256 of the circuit's JSON form, so a
+change of the circuit generators shows up as a stale fixture;
+`--meta-only` rewrites only that record for entries already stored.
 """
+import hashlib
 import json
 import os
 import sys
@@ -25,11 +29,20 @@ from paper_2208_01498_amd.planner.plan import make_plan  # noqa: E402
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fullsize_oracle_amplitudes.json")
 
 
-def main(names):
+def circuit_sha256(circ):
+    return hashlib.sha256(circ.to_json().encode()).hexdigest()
+
+
+def main(names, meta_only=False):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
         circ, words, _ = make_config(name)
         words = [int(w) for w in words[:4]]
+        if meta_only:
+            if name in data:
+                data[name]["circuit_sha256"] = circuit_sha256(circ)
+                json.dump(data, open(OUT, "w"), indent=1)
+            continue
         # order and slices for tensors of at most 2^27 entries (2 GiB in
         # complex128)
         plan = make_plan(circ, n_slices=None, target_width=27, B=1, objective="oracle", trials=1)
@@ -43,9 +56,13 @@ def main(names):
             print(name, w, a, "%.0f s" % rows[-1]["seconds"], flush=True)
             data[name] = {"method": "oracle pairwise contraction, complex128, %d sliced wires "
                                     "summed, plan order as data" % len(spec["sliced"]),
+                          "circuit_sha256": circuit_sha256(circ),
                           "amplitudes": rows}
             json.dump(data, open(OUT, "w"), indent=1)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["cfg3", "cfg2"])
+    args = sys.argv[1:]
+    meta = "--meta-only" in args
+    args = [a for a in args if a != "--meta-only"]
+    main(args or ["cfg3", "cfg2"], meta_only=meta)
