@@ -66,6 +66,35 @@ def copy_calibration(nbytes=1 << 30, reps=5):
                       "launches": reps}), flush=True)
 
 
+def stored_oracle_errors(config, words, amps, n):
+    """Errors of the timed step's results for the bitstrings whose oracle
+    amplitudes are stored (complex128, every slice summed, written by the
+    golden script from the oracle alone): plain relative error per result,
+    and the error and |a_ref| in units of the typical magnitude 2^(-n/2)."""
+    path = os.path.join(ROOT, "tests", "golden", "fullsize_oracle_amplitudes.json")
+    if not os.path.exists(path):
+        return None
+    data = json.load(open(path)).get(config)
+    if not data:
+        return None
+    typ = 2.0 ** (-n / 2)
+    rows = []
+    for r in data["amplitudes"]:
+        w = int(r["bitstring"])
+        hit = [i for i in range(len(words)) if int(words[i]) == w]
+        if not hit:
+            continue
+        ref = complex(r["re"], r["im"])
+        err = abs(complex(amps[hit[0]]) - ref)
+        rows.append({"bitstring": str(w), "plain_relative": err / abs(ref),
+                     "err_over_typical": err / typ, "abs_ref_over_typical": abs(ref) / typ})
+    if not rows:
+        return None
+    return {"reference": "stored oracle amplitudes (" + data["method"] + ")",
+            "results": rows,
+            "max_plain_relative": max(x["plain_relative"] for x in rows)}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -257,7 +286,7 @@ def main():
                     help="time the steps without per-launch events (captured HIP graphs replay), "
                          "then run one more step with events for the per-kernel figures: for "
                          "launch-bound workloads")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--serve", action="store_true", help="served mixed stream instead")
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -360,6 +389,7 @@ def main():
                 abs(rec.get("flops_per_amplitude", 0) / (st["algorithmic_flops"] / nb) - 1) < 1e-6):
             roofline["traffic"] = rec["bytes_per_launch"]
             roofline["traffic_note"] = rec["note"]
+    accuracy = stored_oracle_errors(args.config, words, amps, circ.n)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(circ, int(words[0]), seconds=args.cpu_seconds)
@@ -384,6 +414,7 @@ def main():
         "roofline": roofline,
         "achieved_algorithmic_tflops": st["algorithmic_flops"] * args.steps / el / 1e12,
         "permute_roofline": permute,
+        "accuracy": accuracy,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

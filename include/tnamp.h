@@ -254,6 +254,16 @@ int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N,
  * of B for TN_SPLIT_FP16); a call with less than its mode needs returns
  * TN_EINVAL. */
 size_t tn_kernel_cgemm_scratch_bytes(int32_t M, int32_t N, int32_t K, int32_t nbatch, int32_t nb);
+/* How tn_kernel_cgemm (and every plan step of this shape) sums over k, host
+ * only: *kind is the kernel class (0: K-parallel dot product for M*N <= 16,
+ * summed in float64; 1, 2, 3: MFMA tiles of 64x64, 128x128, 128x16 class,
+ * each output element accumulated in FP32 over its K range); *splits is the
+ * number of K ranges of K/splits consecutive k (split-K), whose partial sums
+ * are added in float64 in range order.  The summation order fixes the
+ * rounding error of a step: the accumulation of one element rounds K/splits
+ * times.  TN_EINVAL unless M, N, K are powers of two and nbatch >= 1. */
+int tn_kernel_cgemm_shape(int32_t M, int32_t N, int32_t K, int32_t nbatch, int32_t* kind,
+                          int32_t* splits);
 int tn_kernel_permute(const void* src, void* dst, int32_t rank, const int32_t* perm,
                       int32_t nb, void* hip_stream);
 

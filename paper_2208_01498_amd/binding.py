@@ -22,7 +22,8 @@ PRECISIONS = {"fp32": TN_FP32_4M, "fp32_3m": TN_FP32_3M, "bf16x3": TN_SPLIT_BF16
 EXPORTED = ["tn_ctx_create", "tn_ctx_destroy", "tn_plan_load", "tn_plan_validate",
             "tn_plan_info", "tn_plan_unload", "tn_contract_amplitudes", "tn_submit",
             "tn_poll", "tn_cancel", "tn_server_config", "tn_server_set_heavy", "tn_server_stop",
-            "tn_last_exec_stats", "tn_ctx_set_profiling", "tn_ctx_set_slice_block", "tn_ctx_set_graphs", "tn_kernel_cgemm", "tn_kernel_cgemm_scratch_bytes", "tn_kernel_permute",
+            "tn_last_exec_stats", "tn_ctx_set_profiling", "tn_ctx_set_slice_block", "tn_ctx_set_graphs", "tn_kernel_cgemm", "tn_kernel_cgemm_scratch_bytes", "tn_kernel_cgemm_shape",
+            "tn_kernel_permute",
             "tn_last_error"]
 
 
@@ -96,6 +97,8 @@ def load_library(path=LIB_PATH):
                             ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                             ctypes.c_int64, i32, vp, sz, vp],
         "tn_kernel_permute": [vp, vp, i32, ctypes.POINTER(ctypes.c_int32), i32, vp],
+        "tn_kernel_cgemm_shape": [i32, i32, i32, i32, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -202,6 +205,14 @@ def tn_server_stop(ctx):
 
 def tn_kernel_cgemm_scratch_bytes(M, N, K, nbatch=1, nb=1):
     return load_library().tn_kernel_cgemm_scratch_bytes(M, N, K, nbatch, nb)
+
+
+def tn_kernel_cgemm_shape(M, N, K, nbatch=1):
+    """(kernel class, K ranges) of the GEMM of this shape; host only."""
+    kind, splits = ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().tn_kernel_cgemm_shape(M, N, K, nbatch, ctypes.byref(kind),
+                                                ctypes.byref(splits)))
+    return kind.value, splits.value
 
 
 def tn_kernel_cgemm(A, B, C, M, N, K, transA=0, transB=0, nbatch=1, nb=1, sAb=0, sBb=0,

@@ -37,6 +37,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -793,10 +794,13 @@ k_cgemm3m(GemmArgs g) {
 // Tiny outputs (M*N <= 16), any K: each workgroup sums one K range of one
 // batch entry; the 256 lanes are split into M*N groups of L = 256/(M*N)
 // consecutive lanes, one output per group, lanes striding along k, followed
-// by an LDS tree reduction within each group (fixed order).
+// by an LDS tree reduction within each group (fixed order).  The products
+// of the FP32 operands are exact in float64, and the lane sums and the tree
+// run in float64: the only FP32 rounding is the final store (and the
+// float64 partials of a split K are summed by k_reduce_splitk before it).
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_cgemm_dot(GemmArgs g) {
-    __shared__ float2 red[256];
+    __shared__ double2 red[256];
     size_t blk = blockIdx.x;
     const int split = (int)(blk % g.splits);
     blk /= g.splits;
@@ -815,16 +819,16 @@ __global__ void __launch_bounds__(256) k_cgemm_dot(GemmArgs g) {
     const int tid = threadIdx.x;
     const int o = tid / L, kl = tid % L;
     const int m = o / N, n = o % N;
-    float cr = 0.f, ci = 0.f;
+    double cr = 0.0, ci = 0.0;
     for (int k = kb + kl; k < ke; k += L) {
         const float2 a = TA ? A[(size_t)k * M + m] : A[(size_t)m * g.K + k];
         const float2 b = TB ? B[(size_t)n * g.K + k] : B[(size_t)k * N + n];
-        cr = fmaf(a.x, b.x, cr);
-        cr = fmaf(-a.y, b.y, cr);
-        ci = fmaf(a.x, b.y, ci);
-        ci = fmaf(a.y, b.x, ci);
+        cr = fma((double)a.x, (double)b.x, cr);
+        cr = fma(-(double)a.y, (double)b.y, cr);
+        ci = fma((double)a.x, (double)b.y, ci);
+        ci = fma((double)a.y, (double)b.x, ci);
     }
-    red[tid] = make_float2(cr, ci);
+    red[tid] = make_double2(cr, ci);
     __syncthreads();
     for (int w = L / 2; w > 0; w >>= 1) {
         if (kl < w) {
@@ -834,18 +838,21 @@ __global__ void __launch_bounds__(256) k_cgemm_dot(GemmArgs g) {
         __syncthreads();
     }
     if (kl == 0) {
-        const float2 v = red[tid];
+        const double2 v = red[tid];
         if (g.splits > 1) {
-            g.P[(((size_t)split * n_outer + outer) * g.nbatch + ib) * (size_t)MN + o] = v;
+            g.Pd[(((size_t)split * n_outer + outer) * g.nbatch + ib) * (size_t)MN + o] = v;
         } else {
             float2* C = g.C + bb * g.sCb + ib * g.sCi + rr * g.sCr;
-            C[gemm_c_elem(g, m, n)] = v;
+            C[gemm_c_elem(g, m, n)] = make_float2((float)v.x, (float)v.y);
         }
     }
 }
 
-// Sum of split-K partials in range order, written in C's layout.  Partial
-// layout: [split][outer][inner batch][m'][n'] over the folded sizes.
+// Sum of split-K partials in range order, in float64 and rounded to FP32
+// once, written in C's layout.  Partial layout: [split][outer][inner
+// batch][m'][n'] over the folded sizes; FP32 partials from the MFMA
+// kernels, float64 partials (Pd, same layout) from the dot kernel.
+template <bool DP>
 __global__ void k_reduce_splitk(GemmArgs g) {
     const int Mt = gemm_rows(g);
     const int Nt = gemm_cols(g);
@@ -855,11 +862,17 @@ __global__ void k_reduce_splitk(GemmArgs g) {
     const size_t per = MN * g.nbatch * n_outer;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < per;
          e += (size_t)gridDim.x * blockDim.x) {
-        float2 s = g.P[e];
-        for (int sp = 1; sp < g.splits; ++sp) {
-            const float2 v = g.P[(size_t)sp * per + e];
-            s.x += v.x;
-            s.y += v.y;
+        double sx = 0.0, sy = 0.0;
+        for (int sp = 0; sp < g.splits; ++sp) {
+            if (DP) {
+                const double2 v = g.Pd[(size_t)sp * per + e];
+                sx += v.x;
+                sy += v.y;
+            } else {
+                const float2 v = g.P[(size_t)sp * per + e];
+                sx += (double)v.x;
+                sy += (double)v.y;
+            }
         }
         const size_t mn = e % MN;
         const size_t bi = e / MN;
@@ -870,7 +883,7 @@ __global__ void k_reduce_splitk(GemmArgs g) {
         const size_t c = bb * g.sCb + ib * g.sCi + rr * g.sCr +
                          (size_t)gemm_c_copy(g, (unsigned)(mp >> lgM), (unsigned)(np >> lgN)) +
                          gemm_c_elem(g, m, n);
-        g.C[c] = s;
+        g.C[c] = make_float2((float)sx, (float)sy);
     }
 }
 
@@ -962,8 +975,6 @@ __global__ void __launch_bounds__(256) k_opmax(GemmArgs g, unsigned* out, size_t
 // ---------------------------------------------------------------------------
 // host-side dispatch
 
-static int ilog2(long long x) { int r = 0; while ((1ll << r) < x) ++r; return r; }
-
 GemmChoice choose_gemm(int M, int N, int K, int nbatch, int Mt, int Nt) {
     GemmChoice c{};
     c.swap = 0;
@@ -1001,10 +1012,13 @@ GemmChoice choose_gemm(int M, int N, int K, int nbatch, int Mt, int Nt) {
     return c;
 }
 
+// split-K partials in complex64 units: the dot kernel's partials are
+// complex128 and take two units each
 size_t gemm_scratch_elems(int M, int N, int K, int nbatch, int nouter) {
     GemmChoice c = choose_gemm(M, N, K, nbatch);
     if (c.splits <= 1) return 0;
-    return (size_t)c.splits * nouter * nbatch * (size_t)M * N;
+    const size_t per = c.kind == GEMM_DOT ? 2 : 1;
+    return per * c.splits * nouter * nbatch * (size_t)M * N;
 }
 
 size_t gemm_scale_words(int M, int N, int K, int nbatch, int nouter) {
@@ -1018,12 +1032,11 @@ static void launch_one(const GemmArgs& g, size_t grid, hipStream_t s) {
     using SM = Smem<PREC, WGM, WGN, WMF, WNF>;
     const size_t lds = SM::bytes;
     auto* fn = &k_cgemm<PREC, WGM, WGN, WMF, WNF, TA, TB>;
-    static bool attr = false;       // one per instantiation; a repeated call is harmless
-    if (!attr) {
+    static std::once_flag attr;     // one per instantiation, safe from concurrent slots
+    std::call_once(attr, [&] {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr = true;
-    }
+    });
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64 * WGM * WGN), lds, s, g);
 }
 
@@ -1042,12 +1055,11 @@ template <int WGM, int WGN, int WMF, int WNF, bool TA, bool TB>
 static void launch_one3(const GemmArgs& g, size_t grid, hipStream_t s) {
     const size_t lds = Smem3<WGM, WGN, WMF, WNF>::bytes;
     auto* fn = &k_cgemm3m<WGM, WGN, WMF, WNF, TA, TB>;
-    static bool attr = false;
-    if (!attr) {
+    static std::once_flag attr;
+    std::call_once(attr, [&] {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr = true;
-    }
+    });
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64 * WGM * WGN), lds, s, g);
 }
 
@@ -1098,6 +1110,7 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
     }
     g.splits = c.splits;
     if (c.splits > 1 && !g.P) return hipErrorInvalidValue;
+    g.Pd = reinterpret_cast<double2*>(g.P);
     const int Mt = gemm_rows(g);
     const int Nt = gemm_cols(g);
     const size_t n_outer = g.fold == 0 ? (size_t)g.nr * g.nb : (size_t)g.nb;
@@ -1160,7 +1173,8 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
     if (e != hipSuccess || c.splits <= 1) return e;
     const size_t per = (size_t)Mt * Nt * g.nbatch * n_outer;
     unsigned blocks = (unsigned)std::min<size_t>((per + 255) / 256, 1u << 16);
-    hipLaunchKernelGGL(k_reduce_splitk, dim3(blocks), dim3(256), 0, s, g);
+    if (c.kind == GEMM_DOT) hipLaunchKernelGGL(k_reduce_splitk<true>, dim3(blocks), dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(k_reduce_splitk<false>, dim3(blocks), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 

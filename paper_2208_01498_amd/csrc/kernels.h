@@ -42,6 +42,7 @@ struct GemmArgs {
     const float2* B;
     float2* C;
     float2* P;                // split-K partials (splits x nb x nbatch x M x N)
+    double2* Pd;              // set by the dispatcher: P as float64 partials (dot kernel)
     int splits;               // set by the dispatcher
     int transC;               // C stored [N][M]
     int M, N, K;

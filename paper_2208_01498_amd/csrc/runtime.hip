@@ -115,20 +115,25 @@ static void add_stats(tn_exec_stats& a, const tn_exec_stats& d, int sign) {
 }
 
 // Run the kernels of one chunk: directly the first time a (plan, workspace,
-// chunk, slice block, precision) shape is seen, captured into a HIP graph
-// the second time, replayed with one launch after that.  Graphs are off
+// chunk size, bitstrings in this chunk, slice block, precision) shape is
+// seen, captured into a HIP graph the second time, replayed with one launch
+// after that.  The chunk size is part of the key because the workspace
+// layout (tensor offsets, the bitstring and accumulator slots) is planned
+// for it: a last chunk of 10 bitstrings under a chunk size of 20 does not
+// issue the launches of a call whose chunk size is 10.  Graphs are off
 // while per-launch events are recorded, and once a context holds
 // kMaxGraphs of them.
 static constexpr size_t kMaxGraphs = 256;
 
 template <class F>
-static int run_chunk(tn_ctx* ctx, const tn_plan* plan, const char* ws, int cb, int r, int precision,
-                     hipStream_t stream, bool graphable, tn_exec_stats& es, F&& launches) {
+static int run_chunk(tn_ctx* ctx, const tn_plan* plan, const char* ws, int chunk, int cb, int r,
+                     int precision, hipStream_t stream, bool graphable, tn_exec_stats& es,
+                     F&& launches) {
     graphable = graphable && ctx && ctx->use_graphs;
     hipGraphExec_t replay = nullptr;
     tn_exec_stats delta{};
     bool capture = false;
-    const auto key = std::make_tuple(plan, ws, cb, r, precision);
+    const auto key = std::make_tuple(plan, ws, chunk, cb, r, precision);
     if (graphable) {
         std::lock_guard<std::mutex> g(ctx->gmu);
         auto it = ctx->graphs.find(key);
@@ -427,7 +432,7 @@ int execute(tn_ctx* ctx, const tn_plan* plan, const uint64_t* bits, int nb, int 
         HIPCHK(ctx, launch_finalize(d_acc, cb, p.scale.real(), p.scale.imag(), stream));
         return TN_OK;
         };
-        int rcc = run_chunk(ctx, plan, ws, cb, r, precision, stream, !prof, es, launches);
+        int rcc = run_chunk(ctx, plan, ws, chunk, cb, r, precision, stream, !prof, es, launches);
         if (rcc) return rcc;
         HIPCHK(ctx, hipMemcpyAsync(out + 2 * (size_t)c0, d_acc, sizeof(double2) * cb, hipMemcpyDeviceToHost, stream));
         HIPCHK(ctx, hipStreamSynchronize(stream));
@@ -620,6 +625,18 @@ static size_t cgemm_partial_bytes(int M, int N, int K, int nbatch, int nb) {
 size_t tn_kernel_cgemm_scratch_bytes(int32_t M, int32_t N, int32_t K, int32_t nbatch, int32_t nb) {
     if (!pow2(M) || !pow2(N) || !pow2(K) || nbatch <= 0 || nb <= 0) return 0;
     return cgemm_partial_bytes(M, N, K, nbatch, nb) + gemm_scale_words(M, N, K, nbatch, nb) * 4;
+}
+
+int tn_kernel_cgemm_shape(int32_t M, int32_t N, int32_t K, int32_t nbatch, int32_t* kind,
+                          int32_t* splits) {
+    if (!kind || !splits || !pow2(M) || !pow2(N) || !pow2(K) || nbatch <= 0) {
+        set_error("bad gemm shape (M, N, K must be powers of two)");
+        return TN_EINVAL;
+    }
+    const GemmChoice c = choose_gemm(M, N, K, nbatch);
+    *kind = c.kind;
+    *splits = c.splits;
+    return TN_OK;
 }
 
 int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N, int32_t K,

@@ -202,7 +202,7 @@ struct tn_ctx {
         tn_exec_stats delta{};
         uint64_t stamp = 0;
     };
-    std::map<std::tuple<const tn_plan*, const char*, int, int, int>, GraphEntry> graphs;
+    std::map<std::tuple<const tn_plan*, const char*, int, int, int, int>, GraphEntry> graphs;
     uint64_t graph_clock = 0;
 };
 

@@ -5,6 +5,8 @@ import pytest
 from circuits import lattice_circuit, random_bitstrings
 from oracle import statevector_amplitudes
 
+import fp_error
+
 pytestmark = pytest.mark.gpu
 
 
@@ -25,7 +27,8 @@ def test_graph_replays_equal_direct_runs(prec, block):
     circ = lattice_circuit(4, 4, 10, 1301, "haar", "cz")
     w1 = random_bitstrings(16, 12, 1302)
     w2 = random_bitstrings(16, 12, 1303)
-    blob = _plan(circ, 3, 12).to_blob()
+    plan = _plan(circ, 3, 12)
+    blob = plan.to_blob()
     direct = B.Engine(0, arena_bytes=128 << 20)
     graphed = B.Engine(0, arena_bytes=128 << 20)
     try:
@@ -45,8 +48,8 @@ def test_graph_replays_equal_direct_runs(prec, block):
         tol = 1e-5 if prec in (0, 1) else 1e-3
         for which, w in ((0, w1), (1, w2)):
             sv = statevector_amplitudes(circ, w)
-            err = np.abs(ref[which] - sv) / np.maximum(np.abs(sv), 2.0 ** (-8))
-            assert err.max() <= tol
+            fp_error.check(ref[which], sv, 2.0 ** -8, tol, fp_error.floor(plan, prec, 2.0 ** -8),
+                           "graphs set %d prec %d" % (which, prec))
     finally:
         direct.close()
         graphed.close()
@@ -81,3 +84,93 @@ def test_graphs_over_chunks_and_unload():
     finally:
         ref_eng.close()
         eng.close()
+
+
+def _small_arena_engine(B, blob, chunk_target):
+    info = B.tn_plan_validate(blob)
+    arena = int(max(1 << 20, info["peak_bytes_fixed"] + (chunk_target + 0.5) * info["peak_bytes_per_b"]))
+    eng = B.Engine(0, arena_bytes=arena)
+    B.tn_ctx_set_slice_block(eng.ctx, 0)
+    return eng, arena
+
+
+@pytest.mark.parametrize("prec", [0, 3])
+def test_graph_key_includes_chunk_size(prec):
+    """A call of c + c/2 bitstrings runs chunks of c and c/2; a call of c/2
+    runs one chunk of c/2 under a layout planned for c/2.  The two last
+    chunks have the same bitstring count but different workspace layouts, so
+    alternating the calls (direct, captured, replayed) must never replay one
+    layout's graph for the other: every result is bitwise the graphs-off
+    result on the same arena, and matches the state vector."""
+    from paper_2208_01498_amd import binding as B
+    circ = lattice_circuit(5, 5, 10, 1321, "haar", "cz")
+    words = random_bitstrings(25, 48, 1322)
+    plan = _plan(circ, 2, 48)
+    blob = plan.to_blob()
+    eng, arena = _small_arena_engine(B, blob, 20)
+    ref_eng = B.Engine(0, arena_bytes=arena)
+    try:
+        B.tn_ctx_set_slice_block(ref_eng.ctx, 0)
+        B.tn_ctx_set_graphs(ref_eng.ctx, 0)
+        p, pr = eng.load(blob), ref_eng.load(blob)
+        eng.amplitudes(p, words, prec)
+        c = B.tn_last_exec_stats(eng.ctx)["chunk"]
+        print("chunk", c, "arena", arena, flush=True)
+        assert 4 <= c < 48
+        sizes = [c + c // 2, c // 2]
+        ref = {n: ref_eng.amplitudes(pr, words[:n], prec) for n in sizes}
+        for call in range(8):
+            n = sizes[call % 2]
+            got = eng.amplitudes(p, words[:n], prec)
+            st = B.tn_last_exec_stats(eng.ctx)
+            print("call", call, "nb", n, "chunk", st["chunk"], "chunks", st["n_chunks"],
+                  "replays", st["graph_replays"], flush=True)
+            assert np.array_equal(got, ref[n]), (call, n)
+        sv = statevector_amplitudes(circ, words[:sizes[0]])
+        typ = 2.0 ** (-circ.n / 2)
+        fp_error.check(ref[sizes[0]], sv, typ, 1e-5 if prec == 0 else 1e-3,
+                       fp_error.floor(plan, prec, typ), "chunk-key prec %d" % prec)
+    finally:
+        eng.close()
+        ref_eng.close()
+
+
+def test_served_batches_of_different_sizes_replay_their_own_graphs():
+    """One slot, so every served batch starts at the same arena offset;
+    batches of c + c/2 and c/2 bitstrings alternate (each waits for the
+    previous one), and every result is bitwise the graphs-off direct run."""
+    import time
+    from paper_2208_01498_amd import binding as B
+    circ = lattice_circuit(5, 5, 10, 1331, "haar", "cz")
+    words = random_bitstrings(25, 48, 1332)
+    blob = _plan(circ, 2, 48).to_blob()
+    # a served batch takes at most half the arena, so the graphs-off
+    # reference runs on half of it and chunks exactly as the server does
+    eng, arena = _small_arena_engine(B, blob, 40)
+    ref_eng = B.Engine(0, arena_bytes=arena // 2)
+    try:
+        B.tn_server_config(eng.ctx, 1, 64)
+        B.tn_ctx_set_slice_block(ref_eng.ctx, 0)
+        B.tn_ctx_set_graphs(ref_eng.ctx, 0)
+        p, pr = eng.load(blob), ref_eng.load(blob)
+        ref_eng.amplitudes(pr, words, 0)
+        c = B.tn_last_exec_stats(ref_eng.ctx)["chunk"]
+        print("served chunk", c, "arena", arena, flush=True)
+        assert 4 <= c < 48
+        sizes = [c + c // 2, c // 2]
+        ref = {n: ref_eng.amplitudes(pr, words[:n], 0) for n in sizes}
+        for call in range(8):
+            n = sizes[call % 2]
+            t = B.tn_submit(eng.ctx, p, words[:n], 0)
+            deadline = time.time() + 60
+            res = None
+            while res is None:
+                assert time.time() < deadline, "served batch did not finish"
+                res = B.tn_poll(eng.ctx, t, n)
+                if res is None:
+                    time.sleep(0.002)
+            print("served call", call, "nb", n, flush=True)
+            assert np.array_equal(res[0], ref[n]), (call, n)
+    finally:
+        eng.close()
+        ref_eng.close()

@@ -7,6 +7,8 @@ from circuits import (make_config, lattice_circuit, stack3d_circuit, iqp_lattice
                       sycamore_type_circuit)
 from oracle import statevector_amplitudes, pairwise_amplitudes
 
+import fp_error
+
 pytestmark = pytest.mark.gpu
 
 TOL = {0: 1e-5, 1: 1e-5, 2: 1e-3, 3: 1e-3, 4: 2e-2}   # 4: plain bf16 rounding, kernel check only
@@ -28,13 +30,13 @@ def _plan(circ, ns=0, B=8, **kw):
     return make_plan(circ, n_slices=ns, B=B, **kw)
 
 
-def _relerr(got, ref, n):
-    """|a - a_ref| / max(|a_ref|, 2^{-n/2}): the relative error for amplitudes
-    at or above the typical magnitude 2^{-n/2}, the error in units of that
-    magnitude below it (single-precision arithmetic has an absolute error
-    floor set by the typical magnitude, so the plain relative error of an
-    amplitude far below it is not bounded by the arithmetic)."""
-    return np.abs(got - ref) / np.maximum(np.abs(ref), 2.0 ** (-n / 2))
+def _judge(got, ref, n, plan, prec, label, typical=None):
+    """Per-result parity against the oracle: plain relative error within
+    TOL[prec] wherever that lies above the rounding floor the plan's
+    arithmetic implies (fp_error), the floor below it, the tail under
+    1e-2 typical in units of the typical magnitude 2^(-n/2)."""
+    typical = 2.0 ** (-n / 2) if typical is None else typical
+    return fp_error.check(got, ref, typical, TOL[prec], fp_error.floor(plan, prec, typical), label)
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2, 3])
@@ -46,9 +48,7 @@ def test_cfg1_all_bitstrings(eng, prec, ns):
     p = eng.load(plan.to_blob())
     got = eng.amplitudes(p, words, prec)
     ref = statevector_amplitudes(circ, words)
-    err = _relerr(got, ref, circ.n)
-    print("max rel err", err.max(), flush=True)
-    assert err.max() <= TOL[prec]
+    _judge(got, ref, circ.n, plan, prec, "cfg1 prec %d slices %d" % (prec, ns))
 
 
 FAMILIES = [
@@ -74,8 +74,7 @@ def test_families_vs_statevector(eng, name, mk, ns, prec):
     p = eng.load(plan.to_blob())
     got = eng.amplitudes(p, words, prec)
     ref = statevector_amplitudes(circ, words)
-    err = _relerr(got, ref, circ.n)
-    assert err.max() <= TOL[prec], err.max()
+    _judge(got, ref, circ.n, plan, prec, "%s slices %d prec %d" % (name, ns, prec))
 
 
 @pytest.mark.parametrize("prec", [0, 3])
@@ -231,7 +230,7 @@ def test_slice_block_is_bitwise_invariant():
         for r in res:
             assert np.array_equal(res[r], res[0]), r
         ref = statevector_amplitudes(circ, words)
-        assert _relerr(res[0], ref, circ.n).max() <= 1e-5
+        _judge(res[0], ref, circ.n, plan, 0, "4x4 d10 2^5 slices prec 0")
         # the 3M and split paths too
         for prec in (1, 2, 3):
             B.tn_ctx_set_slice_block(eng.ctx, 0)
@@ -239,7 +238,7 @@ def test_slice_block_is_bitwise_invariant():
             B.tn_ctx_set_slice_block(eng.ctx, 5)
             b = eng.amplitudes(p, words, prec)
             assert np.array_equal(a, b), prec
-            assert _relerr(a, ref, circ.n).max() <= TOL[prec]
+            _judge(a, ref, circ.n, plan, prec, "4x4 d10 2^5 slices prec %d" % prec)
     finally:
         eng.close()
 
@@ -276,8 +275,8 @@ def test_projector_mode_vs_doubled_oracle(eng, traced, prec):
     got = eng.amplitudes(eng.load(plan.to_blob()), words, prec)
     ref = np.array([doubled_expectation(circ, _projectors(circ.n, w, traced), method="statevector")
                     for w in words])
-    err = np.abs(got - ref) / np.maximum(np.abs(ref), 2.0 ** (-(circ.n - len(traced))))
-    print("max err", err.max(), flush=True)
-    assert err.max() <= TOL[prec]
+    # c is a probability of n - |traced| projected bits: typical size 2^-(n - |traced|)
+    _judge(got, ref, circ.n, plan, prec, "projector traced %d prec %d" % (len(traced), prec),
+           typical=2.0 ** (-(circ.n - len(traced))))
     if len(traced) == circ.n - 2:
         assert abs(got.sum() - 1) <= 1e-5

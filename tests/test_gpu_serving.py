@@ -7,6 +7,8 @@ import pytest
 from circuits import lattice_circuit, stack3d_circuit, random_bitstrings
 from oracle import statevector_amplitudes
 
+import fp_error
+
 pytestmark = pytest.mark.gpu
 
 
@@ -64,10 +66,11 @@ def test_mixed_stream_equals_alone_runs(prec):
             assert st["t_arrive_ns"] <= st["t_admit_ns"] <= st["t_start_ns"] <= st["t_end_ns"]
             merged += st["batch"] > len(w)
         print("requests served inside a merged batch:", merged, flush=True)
-        for (k, w), a in zip(reqs[:6], alone[:6]):
+        for i, ((k, w), a) in enumerate(zip(reqs, alone)):
             ref = statevector_amplitudes(circs[k], w)
-            err = np.abs(a - ref) / np.maximum(np.abs(ref), 2.0 ** (-circs[k].n / 2))
-            assert err.max() <= (1e-5 if prec == 0 else 1e-3)
+            typ = 2.0 ** (-circs[k].n / 2)
+            fp_error.check(a, ref, typ, 1e-5 if prec == 0 else 1e-3,
+                           fp_error.floor(plans[k], prec, typ), "request %d plan %d" % (i, k))
     finally:
         eng.close()
 
