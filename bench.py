@@ -279,7 +279,10 @@ def main():
     ap.add_argument("--precision", default="fp32_3m", choices=["fp32", "fp32_3m", "bf16x3", "fp16x3", "bf16x1"])
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--slices", type=int, default=10)
-    ap.add_argument("--width", type=float, default=None)
+    ap.add_argument("--width", type=float, default=None,
+                    help="slice until the widest per-slice tensor has 2^width entries")
+    ap.add_argument("--per-bitstring-width", action="store_true",
+                    help="--width counts one bitstring's entries (the batch runs in chunks)")
     ap.add_argument("--arena-gb", type=float, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-after", action="store_true",
@@ -321,7 +324,8 @@ def main():
         words = words[:args.batch]
     nb = len(words)
     t = time.perf_counter()
-    plan = make_plan(circ, n_slices=args.slices, target_width=args.width, B=nb, seed=args.seed)
+    plan = make_plan(circ, n_slices=args.slices, target_width=args.width, B=nb, seed=args.seed,
+                     width_per_bitstring=args.per_bitstring_width)
     blob = plan.to_blob()
     log("plan built in %.1f s: %d leaves, %d steps, %d sliced labels" %
         (time.perf_counter() - t, plan.stats["n_leaves"], plan.stats["n_steps"], len(plan.sliced)))

@@ -105,10 +105,11 @@ class Plan:
 
 def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
               n_circles=24, trials=3, objective="time", coarsen=0, projector=None,
-              top_exact=13, centerpoint="lp"):
+              top_exact=13, centerpoint="lp", width_per_bitstring=False):
     """Build a plan.  ``n_slices``: number of sliced labels (log2 of the slice
     count), or None to slice until the widest per-slice intermediate is at
-    most ``target_width`` (log2 elements, batch included).  ``projector``:
+    most ``target_width`` (log2 elements, batch included; per bitstring with
+    ``width_per_bitstring``, when the batch runs in chunks).  ``projector``:
     None for amplitudes <x|C|0>; otherwise the set of traced qubits of the
     projector quantity <0|C^dag (x)_q P_q C|0> (P_q = |x_q><x_q| elsewhere).
     ``top_exact``: size of the frontier below the root whose pairwise order
@@ -132,28 +133,33 @@ def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
             # a network that falls apart (the two layers of a doubled
             # network with every qubit projected) gets one hierarchy and one
             # exact top order per component; component results multiply last
-            roots = []
-            for grp in tb.component_groups():
-                r = tb.build(grp)
-                if top_exact:
-                    r = refine_top(r, tb, B=B, frontier=top_exact)
-                roots.append(r)
-            root = roots[0] if len(roots) == 1 else tb.greedy(roots)
-            steps = tree_steps(root, len(net.factors))
-            # Trials compete on the cost that is actually executed: the
-            # summed cost over all slices when slicing is asked for, the
-            # unsliced Eq. (3) cost otherwise.
-            sliced, sm = [], None
-            if steps:
-                sm = SliceModel(net, steps, B=B, objective=objective)
-                if do_slice:
-                    sliced, _, _ = sm.greedy(n_slices=n_slices if n_slices else None,
-                                             target_width=target_width)
-                cost = sm.evaluate(sliced, ordered=True)[0]
-            else:
-                cost = plan_stats(net, steps, B=1)["flops"]
-            if best is None or cost < best[0]:
-                best = (cost, steps, net, sliced, sm)
+            base = [tb.build(grp) for grp in tb.component_groups()]
+            # The exact top order weighs merges without a bitstring index by
+            # 1/B.  Under a width cap a large B makes those merges look free
+            # and their wide results are then sliced at a cost the order did
+            # not see, so a cap with a batch above 8 also tries the weight 8;
+            # every candidate is costed at the real B below.
+            weights = [B] + ([8] if target_width is not None and B > 8 and top_exact else [])
+            for wB in weights:
+                roots = [refine_top(r, tb, B=wB, frontier=top_exact) if top_exact else r
+                         for r in base]
+                root = roots[0] if len(roots) == 1 else tb.greedy(roots)
+                steps = tree_steps(root, len(net.factors))
+                # Trials compete on the cost that is actually executed: the
+                # summed cost over all slices when slicing is asked for, the
+                # unsliced Eq. (3) cost otherwise.
+                sliced, sm = [], None
+                if steps:
+                    sm = SliceModel(net, steps, B=B, objective=objective,
+                                    width_with_batch=not width_per_bitstring)
+                    if do_slice:
+                        sliced, _, _ = sm.greedy(n_slices=n_slices if n_slices else None,
+                                                 target_width=target_width)
+                    cost = sm.evaluate(sliced, ordered=True)[0]
+                else:
+                    cost = plan_stats(net, steps, B=1)["flops"]
+                if best is None or cost < best[0]:
+                    best = (cost, steps, net, sliced, sm)
     _, steps, net, sliced, sm = best
     total = None
     predicted = None
@@ -172,4 +178,4 @@ def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
                  n_steps=len(steps))
     return Plan(circ, net, steps, sliced, leaf_order, step_layout, stats,
                 dict(n_slices=n_slices, target_width=target_width, B=B, bottom=bottom,
-                     seed=seed))
+                     seed=seed, width_per_bitstring=width_per_bitstring))

@@ -15,10 +15,14 @@ import math
 
 class SliceModel:
     def __init__(self, net, steps, B=1, peak_flops=157.3e12 * 0.6, peak_bw=8.0e12 * 0.6,
-                 launch=4e-6, objective="time", blocked=True):
+                 launch=4e-6, objective="time", blocked=True, width_with_batch=True):
         self.net = net
         self.steps = steps
         self.B = B
+        # the width a target is compared with: log2 elements of the widest
+        # per-slice tensor with its bitstring batch, or per bitstring (the
+        # executor then runs the batch in chunks that fit the arena)
+        self.width_with_batch = width_with_batch
         self.blocked = blocked
         self.peak_flops, self.peak_bw, self.launch = peak_flops, peak_bw, launch
         self.objective = objective
@@ -89,7 +93,7 @@ class SliceModel:
 
     def evaluate(self, sliced, ordered=False):
         """(total flops over all slices with reuse, widest per-slice tensor in
-        log2 elements including the batch)."""
+        log2 elements, including the batch unless width_with_batch is off)."""
         S = list(sliced) if ordered else self.order_bits(sliced)
         pos = {l: j for j, l in enumerate(S)}
         Sset = set(S)
@@ -124,7 +128,7 @@ class SliceModel:
                     total += reps * (max(f / self.peak_flops, byt / self.peak_bw) + self.launch)
             else:
                 total += f * reps
-            width = max(width, cb + math.log2(bsz))
+            width = max(width, cb + (math.log2(bsz) if self.width_with_batch else 0.0))
         return total, width
 
     def greedy(self, n_slices=None, target_width=None, max_slices=30):

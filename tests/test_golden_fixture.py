@@ -19,7 +19,10 @@ def test_stored_oracle_fixture_matches_generators(name):
     entry = data[name]
     circ, words, _ = make_config(name)
     assert hashlib.sha256(circ.to_json().encode()).hexdigest() == entry["circuit_sha256"]
-    assert [int(r["bitstring"]) for r in entry["amplitudes"]] == [int(w) for w in words[:4]]
+    stored = [int(r["bitstring"]) for r in entry["amplitudes"]]
+    # the first bitstrings of the batch, in order (16 of the 6x6 workload's 256)
+    assert len(stored) >= (16 if name == "cfg2" else 4)
+    assert stored == [int(w) for w in words[:len(stored)]]
     for r in entry["amplitudes"]:
         a = complex(r["re"], r["im"])
         # a contracted amplitude of a random circuit: finite, nonzero, far below 1

@@ -238,11 +238,13 @@ def _stored(name):
     rows = data[name]["amplitudes"]
     words = np.array([int(r["bitstring"]) for r in rows], dtype=np.uint64)
     ref = np.array([complex(r["re"], r["im"]) for r in rows])
-    circ, _, _ = make_config(name)
+    circ, all_words, _ = make_config(name)
+    # the plans bench.py times: the whole batch's weight, three hierarchy seeds
     if name == "cfg3":
-        plan = _plan(circ, 10, len(words))              # the timed plan shape, 2^10 slices
+        plan = make_plan(circ, n_slices=10, B=len(all_words))
     else:
-        plan = make_plan(circ, n_slices=None, target_width=28, B=len(words), trials=1)
+        plan = make_plan(circ, n_slices=None, target_width=28, B=len(all_words),
+                         width_per_bitstring=True)
         assert plan.stats["max_bits"] <= 28
     return circ, words, ref, plan.to_blob(), plan
 
@@ -259,14 +261,17 @@ def _check_stored(eng, name, prec):
 
 @pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_headline_vs_stored_oracle(eng, prec):
-    """The 8x8 depth-16 workload at its full size, in the timed plan shape
-    (2^10 slices), against complex128 oracle amplitudes of its first
-    bitstrings with every slice summed (stored by the golden script)."""
+    """The 8x8 depth-16 workload at its full size, in the plan bench.py
+    times (2^10 slices, built for its 64 bitstrings), against complex128
+    oracle amplitudes of its first bitstrings with every slice summed
+    (stored by the golden script)."""
     _check_stored(eng, "cfg3", prec)
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_fsim_6x6_depth12_vs_stored_oracle(eng, prec):
-    """The 6x6 depth-12 fSim workload at its full size (per-slice rank at
-    most 28) against stored complex128 oracle amplitudes."""
+    """The 6x6 depth-12 fSim workload at its full size, in the plan bench.py
+    times for its 256 bitstrings (per-bitstring rank at most 28, the batch
+    in chunks), against the stored complex128 oracle amplitudes of its
+    first 16 bitstrings."""
     _check_stored(eng, "cfg2", prec)
