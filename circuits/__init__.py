@@ -22,7 +22,8 @@ from .families import (lattice_circuit, iqp_lattice_circuit, stack3d_circuit,
                        random_bitstrings, pack_bits, unpack_bits,
                        circuit_seed, bitstring_seed, paper_iqp_circuit,
                        sycamore_type_circuit, paper_family_instances,
-                       sycamore_type_gate_counts, cavity_circuit_gate_counts)
+                       sycamore_type_gate_counts, cavity_circuit_gate_counts,
+                       cavity_circuit)
 
 __all__ = [
     "H", "SQRT_X", "SQRT_Y", "SQRT_W", "CZ", "z_phase", "cphase", "fsim",
@@ -31,5 +32,5 @@ __all__ = [
     "make_config", "config_names", "random_bitstrings", "pack_bits",
     "unpack_bits", "circuit_seed", "bitstring_seed", "paper_iqp_circuit",
     "sycamore_type_circuit", "paper_family_instances", "sycamore_type_gate_counts",
-    "cavity_circuit_gate_counts",
+    "cavity_circuit_gate_counts", "cavity_circuit",
 ]

@@ -175,12 +175,16 @@ def sycamore_type_circuit(L, periods, p_inaccessible, seed):
 
 def paper_family_instances(L):
     """One seeded realization per family of the paper's examples at size L:
-    (name, circuit, time steps T) for the IQP family (T = L^2, gamma = 3)
-    and the Sycamore-type family (5 periods of 8 cycles; qubits
-    inaccessible with probability 0.88, and 0.5 as a denser variant)."""
+    (name, circuit, time steps T) for the IQP family (T = L^2, gamma = 3),
+    the Sycamore-type family (5 periods of 8 cycles; qubits inaccessible
+    with probability 0.88, and 0.5 as a denser variant) and the
+    (2+1)-dimensional family with cavities (S = 5, sigma = 10,
+    lam = 5e4 (L/200)^3.5) at T = L time steps: the paper's alpha = 0.1
+    gives less than one step below L = 10, so these sizes take alpha = 1."""
     return [("iqp_T=L^2_gamma=3", paper_iqp_circuit(L, L * L, 5200 + L), L * L),
             ("sycamore_type_q=5_p=0.88", sycamore_type_circuit(L, 5, 0.88, 5300 + L), 40),
-            ("sycamore_type_q=5_p=0.5", sycamore_type_circuit(L, 5, 0.5, 5400 + L), 40)]
+            ("sycamore_type_q=5_p=0.5", sycamore_type_circuit(L, 5, 0.5, 5400 + L), 40),
+            ("cavity_T=L_S=5", cavity_circuit(L, 5500 + L, T=L), L)]
 
 
 def _pattern_counts(free, pat):
@@ -218,21 +222,13 @@ def sycamore_type_gate_counts(L, periods, p_inaccessible, seed):
     return f
 
 
-def cavity_circuit_gate_counts(L, seed, alpha=0.1, S=5, sigma=10.0, lam=None):
-    """The paper's third example, (2+1)-dimensional random circuits with
-    cavities, as two-qubit gate counts per qubit (L x L) and the number of
-    time steps T = max(1, round(alpha L)).  Each time step applies one edge
-    pattern of uniformly random orientation and parity (a dense layer of
-    nearest-neighbour gates) to the pairs whose sites are both outside every
-    cavity; v ~ Poisson(lam) cavities of S x S x S space-time sites have
-    uniformly random corners, and each is kept with probability
-    exp(-(x^2/L^2 + y^2/L^2 + t^2/T^2) / sigma^2), with (x, y, t) its centre
-    measured from the centre of the circuit's space-time box.
-    lam = 5e4 (L/200)^3.5 by default."""
-    rng = _rng(seed)
-    T = max(1, int(round(alpha * L)))
-    if lam is None:
-        lam = 5e4 * (L / 200.0) ** 3.5
+def _cavity_layers(L, rng, T, S, sigma, lam):
+    """Space-time layout of the paper's third example: v ~ Poisson(lam)
+    cavities of S x S x S sites (t, x, y) with uniformly random corners,
+    each kept with probability exp(-(x^2/L^2 + y^2/L^2 + t^2/T^2) / sigma^2)
+    for its centre measured from the centre of the T x L x L box; one edge
+    pattern (orientation and parity uniform, as in `_pattern_counts`) per
+    time step.  Returns (free[T, L, L]: site outside every cavity, pats[T])."""
     v = int(rng.poisson(lam))
     corner = np.stack([rng.integers(0, T, v), rng.integers(0, L, v), rng.integers(0, L, v)], axis=1)
     ctr = corner + (S - 1) / 2.0 - np.array([T, L, L]) / 2.0
@@ -252,12 +248,61 @@ def cavity_circuit_gate_counts(L, seed, alpha=0.1, S=5, sigma=10.0, lam=None):
                 py = np.where(dy, hi[:, 2], corner[:, 2])
                 np.add.at(diff, (pt, px, py), sign)
     cover = diff.cumsum(0).cumsum(1).cumsum(2)[:T, :L, :L]
-    free = cover == 0
     pats = rng.integers(0, 4, T)
+    return cover == 0, pats
+
+
+def _cavity_steps(L, alpha, T):
+    return max(1, int(round(alpha * L))) if T is None else int(T)
+
+
+def cavity_circuit_gate_counts(L, seed, alpha=0.1, S=5, sigma=10.0, lam=None, T=None):
+    """The paper's third example, (2+1)-dimensional random circuits with
+    cavities, as two-qubit gate counts per qubit (L x L) and the number of
+    time steps T = max(1, round(alpha L)) (or T as given).  Each time step
+    applies one edge pattern of uniformly random orientation and parity (a
+    dense layer of nearest-neighbour gates) to the pairs whose sites are
+    both outside every cavity (`_cavity_layers`).  lam = 5e4 (L/200)^3.5 by
+    default.  The same realization as `cavity_circuit(L, seed, ...)`."""
+    rng = _rng(seed)
+    T = _cavity_steps(L, alpha, T)
+    if lam is None:
+        lam = 5e4 * (L / 200.0) ** 3.5
+    free, pats = _cavity_layers(L, rng, T, S, sigma, lam)
     f = np.zeros((L, L), dtype=np.int64)
     for t in range(T):
         f += _pattern_counts(free[t], int(pats[t]))
     return f, T
+
+
+def cavity_circuit(L, seed, alpha=0.1, S=5, sigma=10.0, lam=None, T=None):
+    """The paper's third example as a circuit on an L x L lattice
+    (q = r L + c): T time steps (T = max(1, round(alpha L)) unless given),
+    each a dense layer of nearest-neighbour gates on one edge pattern of
+    random orientation and parity, every gate an independent Haar SU(4),
+    except on pairs with a site inside a cavity (`_cavity_layers`).  The
+    cavity draws come first in the seeded stream, so the two-qubit gate
+    counts equal `cavity_circuit_gate_counts(L, seed, ...)`."""
+    rng = _rng(seed)
+    T = _cavity_steps(L, alpha, T)
+    if lam is None:
+        lam = 5e4 * (L / 200.0) ** 3.5
+    free, pats = _cavity_layers(L, rng, T, S, sigma, lam)
+    gates = []
+    for t in range(T):
+        pat = int(pats[t])
+        start = 0 if pat in (0, 1) else 1
+        for a in range(L):
+            for b in range(start, L - 1, 2):
+                # P0/P2: horizontal pair (a, b)-(a, b+1); P1/P3: vertical (b, a)-(b+1, a)
+                (r1, c1), (r2, c2) = (((a, b), (a, b + 1)) if pat in (0, 2)
+                                      else ((b, a), (b + 1, a)))
+                if free[t, r1, c1] and free[t, r2, c2]:
+                    gates.append(Gate((r1 * L + c1, r2 * L + c2), haar_su4(rng), "SU4"))
+    return Circuit(L * L, gates, lattice_positions(L, L), f"cavity{L}x{L}_T{T}",
+                   {"L": L, "T": T, "alpha": alpha, "S": S, "sigma": sigma, "lam": lam,
+                    "seed": seed, "free_sites": int(free.sum()),
+                    "patterns": [int(x) for x in pats]})
 
 
 def stack3d_circuit(X, Y, Z, layers, seed, name=""):

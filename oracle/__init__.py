@@ -24,11 +24,11 @@ order and slicing invariance, mirror circuits and stabilizer magnitudes.
 """
 from .statevector import statevector, statevector_amplitudes
 from .pairwise import (OracleNetwork, pairwise_amplitudes, pairwise_amplitude,
-                       greedy_order, contract_pair)
+                       contract_pair)
 from .iqp import iqp_amplitudes_bruteforce, iqp_amplitudes_transfer
 from .doubled import doubled_expectation
 
 __all__ = ["statevector", "statevector_amplitudes", "OracleNetwork",
-           "pairwise_amplitudes", "pairwise_amplitude", "greedy_order",
+           "pairwise_amplitudes", "pairwise_amplitude",
            "contract_pair", "iqp_amplitudes_bruteforce",
            "iqp_amplitudes_transfer", "doubled_expectation"]

@@ -187,12 +187,6 @@ def _contract_group(items, outside_counts):
     return arr, ls
 
 
-def greedy_order(pieces):
-    """The oracle's own order: contract everything as one group with the
-    smallest-result-first greedy."""
-    return None
-
-
 def _evaluate(pieces, order):
     if order is None:
         arr, ls = _contract_group([(a, l) for a, l, _ in pieces], {})

@@ -13,12 +13,13 @@ supplemental section on the numerical implementation).
   of both halves' indices costs the product of their dimensions (Eq. (3)).
 
 Candidate separators at each split are Algorithm 1's random great circles
-and the median coordinate hyperplanes; among candidates that satisfy the
-balance condition Eq. (2), the one whose merge has the smallest index union
-is kept (the paper accepts the first candidate passing Eqs. (1)-(2)).  When
-all leaves of a cluster sit at one or two points of the time-collapsed
-embedding (one qubit's world line), no sphere separates them, and the cluster
-is split at the median gate index instead.
+and (unless separators="ssa") the median coordinate hyperplanes; among
+candidates that satisfy the balance condition Eq. (2), the one whose merge
+has the smallest index union is kept (the paper accepts the first candidate
+passing Eqs. (1)-(2)).  When all leaves of a cluster sit at one or two
+points of the time-collapsed embedding (one qubit's world line), no sphere
+separates them, and the cluster is split at the median gate index instead.
+`split_sources` counts where each kept split came from.
 """
 import math
 import numpy as np
@@ -36,9 +37,15 @@ class Node:
 
 
 class TreeBuilder:
-    def __init__(self, net, rng, bottom=8, n_circles=24, radius=0.26, centerpoint="radon"):
+    def __init__(self, net, rng, bottom=8, n_circles=24, radius=0.26, centerpoint="radon",
+                 separators="ssa+planes"):
         self.net = net
         self.centerpoint = centerpoint
+        # candidate separators per split: Algorithm 1's spheres and great
+        # circles ("ssa"), plus the median coordinate hyperplanes
+        # ("ssa+planes"); the split source of every kept split is counted
+        self.separators = separators
+        self.split_sources = {"ssa": 0, "ssa_eq1": 0, "plane": 0, "time": 0}
         self.rng = rng
         self.bottom = bottom
         self.n_circles = n_circles
@@ -256,11 +263,13 @@ class TreeBuilder:
             radii = np.full(len(idx), self.radius)
             d = pts.shape[1]
             k = max_overlap(pts, radii)
-            cands = (ssa_candidates(pts, radii, self.rng, self.n_circles, self.centerpoint)
-                     + plane_candidates(pts))
+            cands = [("ssa", c) for c in ssa_candidates(pts, radii, self.rng, self.n_circles,
+                                                        self.centerpoint)]
+            if self.separators == "ssa+planes":
+                cands += [("plane", c) for c in plane_candidates(pts)]
             best = None
             idx_arr = np.array(idx)
-            for sep in cands:
+            for src, sep in cands:
                 side = classify(sep, pts, radii)
                 ok1, ok2 = eq_checks(side, d, k)
                 if not ok2:
@@ -271,11 +280,15 @@ class TreeBuilder:
                     continue
                 key = (0 if ok1 else 1, sc[0])
                 if best is None or key < best[0]:
-                    best = (key, sc[1], sc[2])
+                    best = (key, sc[1], sc[2], src, ok1)
             if best is not None:
                 A, B = best[1], best[2]
+                self.split_sources[best[3]] += 1
+                if best[3] == "ssa" and best[4]:
+                    self.split_sources["ssa_eq1"] += 1
         if A is None:
             A, B = self.time_split(idx)
+            self.split_sources["time"] += 1
         left = self.build(sorted(A))
         right = self.build(sorted(B))
         return self.merge(left, right)

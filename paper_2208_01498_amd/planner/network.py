@@ -97,7 +97,31 @@ def _gate_pos(circ, qs):
     return np.mean([circ.positions[q] for q in qs], axis=0)
 
 
-def build_network(circ, simplify=True, swap_relabel=False, coarsen=0):
+def _svd_halves(m):
+    """A two-qubit gate G[2 o1 + o2, 2 i1 + i2] as two rank-3 halves joined
+    by a bond (the proof of Theorem 2, Fig. 3a): G = sum_k A[o1, i1, k]
+    B[o2, i2, k] from the SVD of G regrouped as a matrix over (o1 i1) x
+    (o2 i2); singular values above 1e-12 of the largest are kept (2 for
+    CZ and CP, 4 for fSim and generic SU(4)) and absorbed into A; the bond
+    is padded with zero columns to a power of two (it becomes one binary
+    label per bit)."""
+    t = m.reshape(2, 2, 2, 2).transpose(0, 2, 1, 3).reshape(4, 4)    # (o1 i1) x (o2 i2)
+    U, S, Vh = np.linalg.svd(t)
+    r = int(np.sum(S > 1e-12 * S[0]))
+    d = 1 if r <= 1 else (2 if r <= 2 else 4)
+    A = np.zeros((4, d), dtype=np.complex128)
+    Bm = np.zeros((4, d), dtype=np.complex128)
+    A[:, :r] = U[:, :r] * S[:r]
+    Bm[:, :r] = Vh[:r, :].T
+    return A.reshape(2, 2, d), Bm.reshape(2, 2, d), d
+
+
+def build_network(circ, simplify=True, swap_relabel=False, coarsen=0, svd_split=False):
+    """The circuit's network.  Diagonal gates keep their wires' labels
+    (hyperedges) unless ``svd_split``, the paper-faithful form of the proof
+    of Theorem 2: every two-qubit gate becomes two rank-3 halves joined by a
+    bond of its Schmidt rank (2 or 4; a bond of 4 is two binary labels),
+    every one-qubit gate a rank-2 tensor, each half placed at its qubit."""
     n = circ.n
     labels = {}
     factors = []
@@ -135,6 +159,23 @@ def build_network(circ, simplify=True, swap_relabel=False, coarsen=0):
 
     for gi, g in enumerate(circ.gates):
         qs = g.qubits
+        if svd_split:
+            if len(qs) == 1:
+                o = new_label(qs[0], gi)
+                add_factor(g.matrix.copy(), [o, cur[qs[0]]], gi, qs)
+                cur[qs[0]] = o
+                continue
+            A, Bh, d = _svd_halves(g.matrix)
+            nb = int(round(np.log2(d)))
+            bond = [new_label(qs[0], gi) for _ in range(nb)]
+            outs = [new_label(q, gi) for q in qs]
+            for b in bond:
+                labels[b].kind = "wire"
+            sh = (2, 2) + (2,) * nb
+            add_factor(A.reshape(sh), [outs[0], cur[qs[0]]] + bond, gi, qs[:1])
+            add_factor(Bh.reshape(sh), [outs[1], cur[qs[1]]] + bond, gi, qs[1:])
+            cur[qs[0]], cur[qs[1]] = outs
+            continue
         if _is_diag(g.matrix):
             d = np.diag(g.matrix).reshape((2,) * len(qs))
             add_factor(d, [cur[q] for q in qs], gi, qs)

@@ -105,7 +105,8 @@ class Plan:
 
 def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
               n_circles=24, trials=3, objective="time", coarsen=0, projector=None,
-              top_exact=13, centerpoint="lp", width_per_bitstring=False):
+              top_exact=13, centerpoint="lp", width_per_bitstring=False,
+              separators="ssa+planes", svd_split=False):
     """Build a plan.  ``n_slices``: number of sliced labels (log2 of the slice
     count), or None to slice until the widest per-slice intermediate is at
     most ``target_width`` (log2 elements, batch included; per bitstring with
@@ -115,21 +116,35 @@ def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
     ``top_exact``: size of the frontier below the root whose pairwise order
     is chosen exactly (0 keeps the hierarchy's order everywhere).
     ``centerpoint``: Algorithm 1's centerpoint by the LP over a random
-    subset ("lp", the paper's route) or by iterated Radon points ("radon")."""
+    subset ("lp", the paper's route) or by iterated Radon points ("radon").
+    ``separators``: the candidates of each split of the hierarchy:
+    Algorithm 1's spheres plus median coordinate hyperplanes
+    ("ssa+planes"), Algorithm 1's alone ("ssa"), or the planar separator of
+    the qubit graph ("planar", see planar.py).  The kept plan's
+    ``stats["split_sources"]`` counts where its splits came from.
+    ``svd_split``: the paper-faithful network of the proof of Theorem 2
+    (rank-3 SVD halves of every two-qubit gate, no diagonal hyperedges)."""
     from .network import _is_swap_diag, build_doubled_network
     forms = [False]
-    if any(len(g.qubits) == 2 and _is_swap_diag(g.matrix) for g in circ.gates):
+    if not svd_split and any(len(g.qubits) == 2 and _is_swap_diag(g.matrix) for g in circ.gates):
         forms.append(True)
     do_slice = bool(n_slices) or target_width is not None
     best = None
     for swap_relabel in forms:
         if projector is None:
-            net = build_network(circ, swap_relabel=swap_relabel, coarsen=coarsen)
+            net = build_network(circ, swap_relabel=swap_relabel, coarsen=coarsen,
+                                svd_split=svd_split)
         else:
             net = build_doubled_network(circ, traced=projector, swap_relabel=swap_relabel)
         for t in range(trials):
-            tb = TreeBuilder(net, np.random.Generator(np.random.PCG64(seed + t)),
-                             bottom=bottom, n_circles=n_circles, centerpoint=centerpoint)
+            if separators == "planar":
+                from .planar import PlanarTreeBuilder
+                tb = PlanarTreeBuilder(net, np.random.Generator(np.random.PCG64(seed + t)),
+                                       bottom=bottom)
+            else:
+                tb = TreeBuilder(net, np.random.Generator(np.random.PCG64(seed + t)),
+                                 bottom=bottom, n_circles=n_circles, centerpoint=centerpoint,
+                                 separators=separators)
             # a network that falls apart (the two layers of a doubled
             # network with every qubit projected) gets one hierarchy and one
             # exact top order per component; component results multiply last
@@ -159,8 +174,8 @@ def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
                 else:
                     cost = plan_stats(net, steps, B=1)["flops"]
                 if best is None or cost < best[0]:
-                    best = (cost, steps, net, sliced, sm)
-    _, steps, net, sliced, sm = best
+                    best = (cost, steps, net, sliced, sm, dict(tb.split_sources))
+    _, steps, net, sliced, sm, sources = best
     total = None
     predicted = None
     if sm is not None:
@@ -175,7 +190,7 @@ def make_plan(circ, n_slices=0, target_width=None, B=1, bottom=40, seed=0,
                  total_flops_per_b=(total / B) if total else st["flops"],
                  predicted=predicted,
                  permute_elems=lay.permute_elems, n_leaves=len(net.factors),
-                 n_steps=len(steps))
+                 n_steps=len(steps), split_sources=sources)
     return Plan(circ, net, steps, sliced, leaf_order, step_layout, stats,
                 dict(n_slices=n_slices, target_width=target_width, B=B, bottom=bottom,
                      seed=seed, width_per_bitstring=width_per_bitstring))

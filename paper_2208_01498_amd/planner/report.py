@@ -11,6 +11,7 @@ single realizations; the paper's figure data and its comparison system are
 not used.
 
 Usage: python -m paper_2208_01498_amd.planner.report [--L 4 5 6] [--json]
+       python -m paper_2208_01498_amd.planner.report --separators
 """
 import argparse
 import json
@@ -25,6 +26,39 @@ def counted_log2(circ, projector=None, trials=3):
     plan = make_plan(circ, B=1, trials=trials, projector=projector)
     flops = plan.stats["total_flops_per_b"]     # 8 real flops per complex multiply-add
     return math.log2(flops / 4.0), plan.stats["max_bits"]
+
+
+SEPARATORS = ("ssa+planes", "ssa", "planar")
+
+
+def separator_rows(cases, trials=3):
+    """Counted cost (log2 scalar operations per amplitude, all slices) of the
+    plans whose hierarchies come from Algorithm 1 with the median coordinate
+    planes beside its candidates (the default), from Algorithm 1 alone, and
+    from planar level separators (planar.py), with the sources of the kept
+    hierarchy's splits.  `cases`: (name, circuit, make_plan keywords)."""
+    rows = []
+    for name, circ, kw in cases:
+        row = {"workload": name, "n": circ.n}
+        for sep in SEPARATORS:
+            plan = make_plan(circ, trials=trials, separators=sep, **kw)
+            row["log2_ops_" + sep] = math.log2(plan.stats["total_flops_per_b"] / 4.0)
+            row["max_rank_" + sep] = plan.stats["max_bits"]
+            row["splits_" + sep] = plan.stats["split_sources"]
+        rows.append(row)
+    return rows
+
+
+def workload_cases():
+    from circuits import make_config, paper_family_instances
+    cases = []
+    for cfg, kw in (("cfg1", dict(n_slices=0, B=8)), ("cfg3", dict(n_slices=10, B=64)),
+                    ("cfg2", dict(n_slices=None, target_width=28, B=256, width_per_bitstring=True)),
+                    ("cfg4", dict(n_slices=0, B=1024))):
+        cases.append((cfg, make_config(cfg)[0], kw))
+    for name, circ, _ in paper_family_instances(6):
+        cases.append((name + "_L6", circ, dict(n_slices=None, target_width=30, B=64)))
+    return cases
 
 
 def family_rows(Ls=(4, 5, 6, 7, 8), doubled=True):
@@ -91,10 +125,27 @@ def main():
     ap.add_argument("--L", type=int, nargs="+", default=[4, 5, 6, 7, 8])
     ap.add_argument("--no-doubled", action="store_true")
     ap.add_argument("--json", action="store_true")
+    ap.add_argument("--separators", action="store_true",
+                    help="counted cost of the workloads' plans under each separator family")
     ap.add_argument("--large", action="store_true",
                     help="bounds only at the paper's large sizes (Sycamore-type L = 200..1600, "
                          "cavity circuits L = 150..300)")
     args = ap.parse_args()
+    if args.separators:
+        rows = separator_rows(workload_cases())
+        if args.json:
+            print(json.dumps(rows))
+            return
+        print("| workload | n | " + " | ".join("log2 ops %s (max rank) | splits %s" % (x, x)
+                                             for x in SEPARATORS) + " |")
+        print("|" + "---|" * (2 + 2 * len(SEPARATORS)))
+        for r in rows:
+            cells = [r["workload"], str(r["n"])]
+            for x in SEPARATORS:
+                cells.append("%.2f (%d)" % (r["log2_ops_" + x], r["max_rank_" + x]))
+                cells.append(", ".join("%s %d" % kv for kv in r["splits_" + x].items() if kv[1]))
+            print("| " + " | ".join(cells) + " |", flush=True)
+        return
     if args.large:
         rows = (crossover_table("sycamore", (200, 400, 800, 1600))
                 + crossover_table("cavity", (150, 200, 250, 300)))

@@ -153,3 +153,30 @@ def test_gate_count_generators_follow_the_circuit_rules():
                 want[a] += 1
                 want[b] += 1
         assert np.array_equal(f, want)
+
+
+@pytest.mark.parametrize("L,T,S,lam", [(4, 4, 5, None), (6, 6, 2, 3.0), (8, 8, 5, 3.0)])
+def test_cavity_circuit_has_the_counted_gates(L, T, S, lam):
+    """The executable cavity circuit and the gate counts of the bound
+    evaluations are one realization: per-qubit two-qubit gate counts agree,
+    every gate is a unitary on a nearest-neighbour pair, and gates inside
+    cavities are missing from the dense layers."""
+    import numpy as np
+    from circuits import cavity_circuit, cavity_circuit_gate_counts
+    c = cavity_circuit(L, 77 + L, T=T, S=S, lam=lam)
+    f, TT = cavity_circuit_gate_counts(L, 77 + L, T=T, S=S, lam=lam)
+    assert TT == T == c.meta["T"]
+    cnt = np.zeros((L, L), dtype=np.int64)
+    for g in c.gates:
+        a, b = g.qubits
+        assert abs(a // L - b // L) + abs(a % L - b % L) == 1
+        assert np.allclose(g.matrix.conj().T @ g.matrix, np.eye(4), atol=1e-12)
+        cnt[a // L, a % L] += 1
+        cnt[b // L, b % L] += 1
+    assert np.array_equal(cnt, f)
+    # the dense layers of the same edge patterns, minus the pairs that touch
+    # a cavity
+    dense = sum(L * (L // 2) if p in (0, 1) else L * ((L - 1) // 2) for p in c.meta["patterns"])
+    assert c.n_2q() <= dense
+    if S == 2 and lam:
+        assert c.meta["free_sites"] < L * L * T and c.n_2q() < dense

@@ -275,3 +275,32 @@ def test_fsim_6x6_depth12_vs_stored_oracle(eng, prec):
     in chunks), against the stored complex128 oracle amplitudes of its
     first 16 bitstrings."""
     _check_stored(eng, "cfg2", prec)
+
+
+def test_iqp48_paper_form_sliced_to_fit_64gb():
+    """The IQP workload in the paper-faithful network of the proof of
+    Theorem 2 (every CP split into rank-3 SVD halves with a bond of its
+    Schmidt rank 2, no diagonal hyperedges): sliced until one bitstring's
+    per-slice tensors have at most 2^30 entries, run in a 64 GiB arena (the
+    executor chunks the batch to fit), 4 bitstrings against the
+    transfer-matrix closed form."""
+    from paper_2208_01498_amd import binding as B
+    from paper_2208_01498_amd.planner.plan import make_plan
+    circ, words, _ = make_config("cfg4")
+    words = words[:4]
+    plan = make_plan(circ, n_slices=None, target_width=30, B=len(words), width_per_bitstring=True,
+                     svd_split=True, trials=1)
+    blob = plan.to_blob()
+    info = B.tn_plan_validate(blob)
+    print("svd form: %d leaves, %d slices, 2^%.2f flops per amplitude, %.1f GB per bitstring"
+          % (info["n_leaves"], 1 << info["n_sliced"], np.log2(info["flops_total_per_b"]),
+             info["peak_bytes_per_b"] / 1e9), flush=True)
+    assert info["n_sliced"] >= 1 and info["peak_bytes_fixed"] + info["peak_bytes_per_b"] <= 64 << 30
+    e = B.Engine(0, arena_bytes=64 << 30)
+    try:
+        got = e.amplitudes(e.load(blob), words, B.TN_FP32_3M)
+        st = B.tn_last_exec_stats(e.ctx)
+        print("chunk", st["chunk"], "chunks", st["n_chunks"], "slice block", st["slice_block"], flush=True)
+    finally:
+        e.close()
+    _judge(got, iqp_amplitudes_transfer(circ, words), circ.n, plan, B.TN_FP32_3M, "iqp 6x8 svd form")

@@ -4,7 +4,7 @@ import pytest
 
 from circuits import (make_config, lattice_circuit, stack3d_circuit, iqp_lattice_circuit,
                       random_bitstrings, mirror, product_circuit, paper_iqp_circuit,
-                      sycamore_type_circuit)
+                      sycamore_type_circuit, cavity_circuit)
 from oracle import statevector_amplitudes, pairwise_amplitudes
 
 import fp_error
@@ -60,6 +60,7 @@ FAMILIES = [
     ("product_8", lambda: product_circuit(8, 3, 206)),
     ("paper_iqp_4x4_T16", lambda: paper_iqp_circuit(4, 16, 207)),
     ("sycamore_type_4x4_p05", lambda: sycamore_type_circuit(4, 5, 0.5, 208)),
+    ("cavity_4x4_T10_S2", lambda: cavity_circuit(4, 209, T=10, S=2, lam=3.0)),
 ]
 
 

@@ -217,3 +217,18 @@ def test_porter_thomas_mean():
     amps = statevector_amplitudes(c, words, psi)
     m = np.mean((1 << 16) * np.abs(amps) ** 2)
     assert abs(m - 1) < 0.1
+
+
+def test_dense_and_hyperedge_forms_agree_at_25_qubits():
+    """The stored 8x8 depth-16 values use the oracle's exact re-labelling of
+    diagonal gates (one wire label shared across a CZ); here the plain dense
+    form (every gate its own rank-2 or rank-4 tensor, as the oracle's
+    definition has it) gives the same amplitude at 25 qubits on the same
+    Haar SU(2) + CZ family, in a plan's order imported as data."""
+    from paper_2208_01498_amd.planner.plan import make_plan
+    circ = lattice_circuit(5, 5, 10, 5100, "haar", "cz")
+    spec = make_plan(circ, n_slices=0, B=1, trials=1).order_spec()
+    w = random_bitstrings(25, 1, 7)
+    a = pairwise_amplitudes(circ, w, order=spec, diagonal_hyperedges=True)
+    b = pairwise_amplitudes(circ, w, order=spec, diagonal_hyperedges=False)
+    assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()

@@ -383,3 +383,51 @@ def test_ssa_candidates_with_centerpoint_on_a_shared_point():
     assert seps
     for kind, a, b in seps:
         assert np.all(np.isfinite(a)) and np.isfinite(b)
+
+
+@pytest.mark.parametrize("name,mk", CIRCS[:5], ids=[c[0] for c in CIRCS[:5]])
+def test_planar_separator_plans_are_exact(name, mk):
+    """Plans whose hierarchy comes from planar level separators (qubit-graph
+    BFS levels) are the same contraction, evaluated by the oracle in their
+    order, with slices."""
+    circ = mk()
+    words = random_bitstrings(circ.n, 3, 930)
+    plan = make_plan(circ, n_slices=2, B=3, separators="planar", bottom=8)
+    spec = plan.order_spec()
+    got = pairwise_amplitudes(circ, words, order=spec, sliced=spec["sliced"])
+    ref = statevector_amplitudes(circ, words)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_planar_levels_are_balanced_and_thin_on_a_lattice():
+    """On an 8x8 lattice network the first planar level split leaves at most
+    2n/3 leaves on either side and its separator is one BFS front of the
+    qubit lattice: at most 8 qubits (sqrt(N) for N = 64); nearly every later
+    split is balanced too."""
+    from paper_2208_01498_amd.planner.planar import PlanarTreeBuilder
+    circ = lattice_circuit(8, 8, 8, 931, "haar", "cz")
+    net = build_network(circ)
+    tb = PlanarTreeBuilder(net, np.random.Generator(np.random.PCG64(0)), bottom=8)
+    idx = list(range(len(net.factors)))
+    A, B, balanced = tb.level_split(idx)
+    assert balanced
+    n = len(idx)
+    assert max(len(A), len(B)) <= 2 * n / 3 + 1e-9 and len(A) + len(B) == n
+    qa = set().union(*(tb._qubits(i) for i in A))
+    qb = set().union(*(tb._qubits(i) for i in B))
+    assert len(qa & qb) <= 8
+    # deeper down, a few small clusters have no level that balances them
+    # (the cycle phase of the Lipton-Tarjan construction is not built)
+    tb.build(idx)
+    assert tb.split_sources["planar"] >= 10 * tb.split_sources["planar_unbalanced"]
+
+
+def test_split_sources_are_counted():
+    """The kept hierarchy reports where its splits came from; without the
+    median planes none comes from them."""
+    circ = make_config("cfg1")[0]
+    a = make_plan(circ, n_slices=0, B=8)
+    b = make_plan(circ, n_slices=0, B=8, separators="ssa")
+    assert sum(a.stats["split_sources"][k] for k in ("ssa", "plane", "time")) >= 1
+    assert a.stats["split_sources"]["ssa_eq1"] <= a.stats["split_sources"]["ssa"]
+    assert b.stats["split_sources"]["plane"] == 0
