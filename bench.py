@@ -150,6 +150,7 @@ def serve_bench(args):
     free, _ = torch.cuda.mem_get_info(0)
     eng = B.Engine(0, arena_bytes=int(free - (8 << 30)))
     B.tn_server_config(eng.ctx, args.slots, 64)
+    B.tn_server_set_heavy(eng.ctx, 1e14, args.max_heavy)
     hs = [eng.load(p.to_blob()) for p in plans]
     fams = sorted(set(f for f, _, _ in pool))
     # time per bitstring of each family, alone (first instance, 8 bitstrings)
@@ -179,6 +180,11 @@ def serve_bench(args):
     reqs = [draw(1000 + i) for i in range(args.serve_requests)]
     gaps = rng.exponential(1.0 / lam, size=len(reqs))
     arrivals = np.cumsum(gaps) - gaps[0]
+    # requests arriving after the cap are not submitted; the stream drains
+    cap = args.serve_cap_s
+    n_sub = int(np.searchsorted(arrivals, cap, side="right")) if cap > 0 else len(reqs)
+    reqs, arrivals = reqs[:n_sub], arrivals[:n_sub]
+    log("%d requests arrive within the %.0f s cap" % (len(reqs), cap))
     t0 = time.perf_counter()
     pending = {}
     done = {}
@@ -202,11 +208,24 @@ def serve_bench(args):
     el = time.perf_counter() - t0
     lat = np.array([(done[j][1]["t_end_ns"] - done[j][1]["t_arrive_ns"]) * 1e-9 for j in range(len(reqs))])
     amps = sum(len(w) for _, w in reqs)
-    # the same request alone gives the same numbers
+    # every served result against the same bitstrings run alone: one call
+    # per plan over all of its requests' bitstrings (a result does not
+    # depend on the batch or chunk it runs in)
     same = True
-    for j in range(min(6, len(reqs))):
-        k, w = reqs[j]
-        same &= bool(np.array_equal(eng.amplitudes(hs[k], w, prec), done[j][0]))
+    mismatched = 0
+    for k in sorted(set(k for k, _ in reqs)):
+        js = [j for j, (kk, _) in enumerate(reqs) if kk == k]
+        allw = np.concatenate([reqs[j][1] for j in js])
+        alone = eng.amplitudes(hs[k], allw, prec)
+        pos = 0
+        for j in js:
+            nb_j = len(reqs[j][1])
+            ok = bool(np.array_equal(alone[pos:pos + nb_j], done[j][0]))
+            mismatched += not ok
+            same &= ok
+            pos += nb_j
+        log("plan %d (%s): %d requests, %d bitstrings checked against the alone run"
+            % (k, pool[k][0], len(js), len(allw)))
     per_fam = {}
     for j, (k, w) in enumerate(reqs):
         per_fam.setdefault(pool[k][0], []).append(lat[j])
@@ -214,7 +233,10 @@ def serve_bench(args):
            "p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
            "req_per_s": len(reqs) / el, "amplitudes_per_s": amps / el,
            "lambda_req_per_s": lam, "saturation_req_per_s": sat, "load": args.serve_load,
-           "n_requests": len(reqs), "slots": args.slots, "alone_equals_mixed": same,
+           "n_requests": len(reqs), "cap_s": cap, "slots": args.slots,
+           "max_heavy": args.max_heavy,
+           "alone_equals_mixed": same, "checked_against_alone": len(reqs),
+           "mismatched": mismatched,
            "precision": args.precision,
            "seconds_per_bitstring_alone": per_b,
            "p50_by_family": {f: float(np.percentile(v, 50)) for f, v in per_fam.items()},
@@ -283,6 +305,9 @@ def main():
                     help="slice until the widest per-slice tensor has 2^width entries")
     ap.add_argument("--per-bitstring-width", action="store_true",
                     help="--width counts one bitstring's entries (the batch runs in chunks)")
+    ap.add_argument("--svd-split", action="store_true",
+                    help="the paper-faithful network: rank-3 SVD halves of every two-qubit gate, "
+                         "no diagonal hyperedges")
     ap.add_argument("--arena-gb", type=float, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-after", action="store_true",
@@ -292,10 +317,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--serve", action="store_true", help="served mixed stream instead")
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="arrival rate as a fraction of the saturation rate")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--max-heavy", type=int, default=2,
+                    help="served batches of at least 1e14 flops running at once")
+    ap.add_argument("--serve-cap-s", type=float, default=600.0,
+                    help="submit only requests arriving within this many seconds (0: all)")
     ap.add_argument("--paper-families", action="store_true",
                     help="the paper's IQP and Sycamore-type families at L = 4..8 instead")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -325,7 +354,7 @@ def main():
     nb = len(words)
     t = time.perf_counter()
     plan = make_plan(circ, n_slices=args.slices, target_width=args.width, B=nb, seed=args.seed,
-                     width_per_bitstring=args.per_bitstring_width)
+                     width_per_bitstring=args.per_bitstring_width, svd_split=args.svd_split)
     blob = plan.to_blob()
     log("plan built in %.1f s: %d leaves, %d steps, %d sliced labels" %
         (time.perf_counter() - t, plan.stats["n_leaves"], plan.stats["n_steps"], len(plan.sliced)))
@@ -414,7 +443,9 @@ def main():
                    "timing": ("steps without per-launch events (graph replays in the last: %d), "
                               "kernel figures from one more step with events" % graph_replays)
                    if args.profile_after else "per-launch events inside the timed steps",
-                   "algorithmic_flops_per_amplitude": st["algorithmic_flops"] / nb},
+                   "algorithmic_flops_per_amplitude": st["algorithmic_flops"] / nb,
+                   "network": "svd halves" if args.svd_split else "diagonal hyperedges",
+                   "arena_bytes": arena},
         "roofline": roofline,
         "achieved_algorithmic_tflops": st["algorithmic_flops"] * args.steps / el / 1e12,
         "permute_roofline": permute,

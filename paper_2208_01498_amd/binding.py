@@ -11,7 +11,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtnamp.so")
+# the in-tree build; TNAMP_LIB names another build of the same sources
+LIB_PATH = os.environ.get("TNAMP_LIB") or os.path.join(HERE, "libtnamp.so")
 
 TN_OK, TN_PENDING = 0, 1
 TN_EINVAL, TN_ENOMEM, TN_EBUSY, TN_EDEVICE, TN_ECANCELLED, TN_ENOTFOUND = -1, -2, -3, -4, -5, -6

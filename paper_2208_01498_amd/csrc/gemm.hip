@@ -50,6 +50,7 @@ namespace {
 constexpr int KT_SPLIT = 8;    // complex k per LDS stage, split modes (one MFMA k-step; keeps
                                // two workgroups per CU)
 constexpr int KT_FP32 = 8;     // complex k per LDS stage, FP32 (keeps two workgroups per CU)
+constexpr int KT_3M = 16;      // complex k per LDS stage, FP32 3M (two real planes per operand)
 constexpr int KT = 16;         // K granularity of the split-K ranges
 
 // bits of x at the set positions of m, compacted (parallel bit extract)
@@ -519,14 +520,17 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
 // same K order as k_cgemm, so a result does not depend on the tile chosen.
 template <int WGM, int WGN, int WMF, int WNF>
 struct Smem3 {
-    static constexpr int KT = KT_FP32;
+    // 16 complex k per stage: the real and imaginary planes only (the sum
+    // plane of 3M is formed from them at read time), double buffered, so
+    // two workgroups still fit a CU
+    static constexpr int KT = KT_3M;
     static constexpr int BM = WGM * 32 * WMF;
     static constexpr int BN = WGN * 32 * WNF;
     // +32 floats per k row: lanes of the two halves of a wave read rows k
     // and k + 1 in disjoint banks
     static constexpr int PA = BM + 32;
     static constexpr int PB = BN + 32;
-    static constexpr size_t bytes = 2 * 3 * (size_t)KT * (PA + PB) * 4;
+    static constexpr size_t bytes = 2 * 2 * (size_t)KT * (PA + PB) * 4;
 };
 
 template <int WGM, int WGN, int WMF, int WNF, bool TA, bool TB>
@@ -649,8 +653,8 @@ k_cgemm3m(GemmArgs g) {
         }
     };
 
-    float* As = reinterpret_cast<float*>(smem);     // [2][3][KT][PA]
-    float* Bs = As + 2 * 3 * KT * PA;               // [2][3][KT][PB]
+    float* As = reinterpret_cast<float*>(smem);     // [2][2][KT][PA]: re, im planes
+    float* Bs = As + 2 * 2 * KT * PA;               // [2][2][KT][PB]
     constexpr int QA = KT * PA, QB = KT * PB;       // plane strides
     // Row k of a plane holds column x at x ^ sw(k), sw(k) = 16 ((k/2) mod 4)
     // (mod the tile width): the four even rows that one store instruction
@@ -661,28 +665,25 @@ k_cgemm3m(GemmArgs g) {
     auto swb = [](int k) { return (((k >> 1) & 3) << 4) & (BN - 1); };
 
     auto store = [&](int buf) {
-        float* a = As + buf * 3 * QA;
-        float* b = Bs + buf * 3 * QB;
+        float* a = As + buf * 2 * QA;
+        float* b = Bs + buf * 2 * QB;
 #pragma unroll
         for (int i = 0; i < LA; ++i) {
             const int f = tid + i * NT;
             if (f >= FA) break;
             const float4 v = ra[i];
             if (TA) {
-                // (m, k), (m + 1, k): adjacent in every plane
+                // (m, k), (m + 1, k): adjacent in both planes
                 const int k = f / (BM / 2), m = 2 * (f % (BM / 2)) ^ swa(k);
                 *reinterpret_cast<float2*>(a + k * PA + m) = make_float2(v.x, v.z);
                 *reinterpret_cast<float2*>(a + QA + k * PA + m) = make_float2(v.y, v.w);
-                *reinterpret_cast<float2*>(a + 2 * QA + k * PA + m) = make_float2(v.x + v.y, v.z + v.w);
             } else {
                 const int m = f / (KT / 2), k = 2 * (f % (KT / 2));
                 const int m0s = m ^ swa(k), m1s = m ^ swa(k + 1);
                 a[k * PA + m0s] = v.x;
                 a[QA + k * PA + m0s] = v.y;
-                a[2 * QA + k * PA + m0s] = v.x + v.y;
                 a[(k + 1) * PA + m1s] = v.z;
                 a[QA + (k + 1) * PA + m1s] = v.w;
-                a[2 * QA + (k + 1) * PA + m1s] = v.z + v.w;
             }
         }
 #pragma unroll
@@ -694,36 +695,41 @@ k_cgemm3m(GemmArgs g) {
                 const int k = f / (BN / 2), n = 2 * (f % (BN / 2)) ^ swb(k);
                 *reinterpret_cast<float2*>(b + k * PB + n) = make_float2(v.x, v.z);
                 *reinterpret_cast<float2*>(b + QB + k * PB + n) = make_float2(v.y, v.w);
-                *reinterpret_cast<float2*>(b + 2 * QB + k * PB + n) = make_float2(v.x + v.y, v.z + v.w);
             } else {
                 const int n = f / (KT / 2), k = 2 * (f % (KT / 2));
                 const int n0s = n ^ swb(k), n1s = n ^ swb(k + 1);
                 b[k * PB + n0s] = v.x;
                 b[QB + k * PB + n0s] = v.y;
-                b[2 * QB + k * PB + n0s] = v.x + v.y;
                 b[(k + 1) * PB + n1s] = v.z;
                 b[QB + (k + 1) * PB + n1s] = v.w;
-                b[2 * QB + (k + 1) * PB + n1s] = v.z + v.w;
             }
         }
     };
 
     auto compute = [&](int buf) {
-        const float* a = As + buf * 3 * QA;
-        const float* b = Bs + buf * 3 * QB;
+        const float* a = As + buf * 2 * QA;
+        const float* b = Bs + buf * 2 * QB;
         // lane (half, l32): A[m = l32][k = half], B[k = half][n = l32];
-        // operands of step ks + 1 are read while the MFMAs of step ks issue
+        // operands of step ks + 1 are read while the MFMAs of step ks issue;
+        // the third operand of 3M is re + im, formed here in FP32 (the same
+        // rounding as when it was staged as a plane)
         float av[2][WMF][3], bv[2][WNF][3];
         auto rd = [&](int ks, int q) {
             const int kr = 2 * ks + half;
 #pragma unroll
-            for (int i = 0; i < WMF; ++i)
+            for (int i = 0; i < WMF; ++i) {
+                const int c = kr * PA + ((wm + i * 32 + l32) ^ swa(kr));
+                av[q][i][0] = a[c];
+                av[q][i][1] = a[QA + c];
+                av[q][i][2] = av[q][i][0] + av[q][i][1];
+            }
 #pragma unroll
-                for (int p = 0; p < 3; ++p) av[q][i][p] = a[p * QA + kr * PA + ((wm + i * 32 + l32) ^ swa(kr))];
-#pragma unroll
-            for (int j = 0; j < WNF; ++j)
-#pragma unroll
-                for (int p = 0; p < 3; ++p) bv[q][j][p] = b[p * QB + kr * PB + ((wn + j * 32 + l32) ^ swb(kr))];
+            for (int j = 0; j < WNF; ++j) {
+                const int c = kr * PB + ((wn + j * 32 + l32) ^ swb(kr));
+                bv[q][j][0] = b[c];
+                bv[q][j][1] = b[QB + c];
+                bv[q][j][2] = bv[q][j][0] + bv[q][j][1];
+            }
         };
         rd(0, 0);
 #pragma unroll

@@ -189,3 +189,41 @@ def test_unload_twice_is_an_error():
         assert e.value.code == B.TN_EINVAL
     finally:
         eng.close()
+
+
+def test_served_mix_families_vs_oracle():
+    """The served mix's circuit families at their sizes (5x5 depth 10 and
+    6x6 depth 12 Haar + CZ lattices, the 3x3x4 SU(4) stack; three instances
+    each, all plans resident; the 8x8 depth-16 family is left to the bench)
+    under a stream of 30 requests of 1-64 bitstrings: every result is
+    bitwise the same bitstrings run alone, and the first four bitstrings of
+    every request match the oracle (pairwise complex128 contraction in the
+    plan's order)."""
+    from circuits.families import serving_pool
+    from oracle import pairwise_amplitudes
+    from paper_2208_01498_amd import binding as B
+    from paper_2208_01498_amd.planner.plan import make_plan
+    pool = [p for p in serving_pool() if p[0] != "8x8d16"]
+    plans = [make_plan(c, n_slices=ns, B=32) for _, c, ns in pool]
+    eng = B.Engine(0, arena_bytes=8 << 30)
+    try:
+        B.tn_server_config(eng.ctx, 4, 64)
+        hs = [eng.load(p.to_blob()) for p in plans]
+        rng = np.random.Generator(np.random.PCG64(5002))
+        reqs = []
+        for i in range(30):
+            k = int(rng.integers(len(pool)))
+            reqs.append((k, random_bitstrings(pool[k][1].n, int(rng.integers(1, 65)), 91000 + i)))
+        print("submitting", len(reqs), "requests on", len(pool), "plans", flush=True)
+        tickets = [B.tn_submit(eng.ctx, hs[k], w, 0) for k, w in reqs]
+        res = _wait(B, eng.ctx, tickets, [len(w) for _, w in reqs], timeout=120)
+        for i, ((k, w), t) in enumerate(zip(reqs, tickets)):
+            got = res[t][0]
+            assert np.array_equal(got, eng.amplitudes(hs[k], w, 0)), i
+            spec = plans[k].order_spec()
+            ref = pairwise_amplitudes(pool[k][1], w[:4], order=spec, sliced=spec["sliced"])
+            typ = 2.0 ** (-pool[k][1].n / 2)
+            fp_error.check(got[:4], ref, typ, 1e-5, fp_error.floor(plans[k], 0, typ),
+                           "served %s request %d" % (pool[k][0], i))
+    finally:
+        eng.close()
