@@ -264,6 +264,24 @@ size_t tn_kernel_cgemm_scratch_bytes(int32_t M, int32_t N, int32_t K, int32_t nb
  * times.  TN_EINVAL unless M, N, K are powers of two and nbatch >= 1. */
 int tn_kernel_cgemm_shape(int32_t M, int32_t N, int32_t K, int32_t nbatch, int32_t* kind,
                           int32_t* splits);
+/* tn_kernel_cgemm without a scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * tn_kernel_cgemm (bitwise); the split-K partials and split fp16 maxima live
+ * in a device array of the library, one per GPU, of
+ * tn_kernel_cgemm_noalloc_max_scratch() bytes (32 MiB), reserved when the
+ * library is loaded on that GPU and held until the process ends.  A shape
+ * whose scratch (tn_kernel_cgemm_scratch_bytes) exceeds it returns TN_EINVAL
+ * before any device work.  Runs on the current device; no call allocates
+ * (no hipMalloc, no allocating library routine).  Every call on one GPU
+ * shares that GPU's array, so calls that overlap on one GPU (concurrent
+ * streams or threads) race; calls ordered on one stream do not.  TN_EDEVICE
+ * if the array's address cannot be found. */
+int tn_kernel_cgemm_noalloc(const void* A, const void* B, void* C, int32_t M, int32_t N,
+                            int32_t K, int32_t transA, int32_t transB, int32_t nbatch,
+                            int32_t nb, int64_t sAb, int64_t sBb, int64_t sCb, int64_t sAi,
+                            int64_t sBi, int64_t sCi, int32_t precision, void* hip_stream);
+size_t tn_kernel_cgemm_noalloc_max_scratch(void);
 int tn_kernel_permute(const void* src, void* dst, int32_t rank, const int32_t* perm,
                       int32_t nb, void* hip_stream);
 

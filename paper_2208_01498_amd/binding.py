@@ -24,7 +24,7 @@ EXPORTED = ["tn_ctx_create", "tn_ctx_destroy", "tn_plan_load", "tn_plan_validate
             "tn_plan_info", "tn_plan_unload", "tn_contract_amplitudes", "tn_submit",
             "tn_poll", "tn_cancel", "tn_server_config", "tn_server_set_heavy", "tn_server_stop",
             "tn_last_exec_stats", "tn_ctx_set_profiling", "tn_ctx_set_slice_block", "tn_ctx_set_graphs", "tn_kernel_cgemm", "tn_kernel_cgemm_scratch_bytes", "tn_kernel_cgemm_shape",
-            "tn_kernel_permute",
+            "tn_kernel_cgemm_noalloc", "tn_kernel_cgemm_noalloc_max_scratch", "tn_kernel_permute",
             "tn_last_error"]
 
 
@@ -100,6 +100,9 @@ def load_library(path=LIB_PATH):
         "tn_kernel_permute": [vp, vp, i32, ctypes.POINTER(ctypes.c_int32), i32, vp],
         "tn_kernel_cgemm_shape": [i32, i32, i32, i32, ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32)],
+        "tn_kernel_cgemm_noalloc": [vp, vp, vp, i32, i32, i32, i32, i32, i32, i32,
+                                    ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                    ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, i32, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -107,6 +110,8 @@ def load_library(path=LIB_PATH):
         f.restype = ctypes.c_int
     lib.tn_kernel_cgemm_scratch_bytes.argtypes = [i32, i32, i32, i32, i32]
     lib.tn_kernel_cgemm_scratch_bytes.restype = ctypes.c_size_t
+    lib.tn_kernel_cgemm_noalloc_max_scratch.argtypes = []
+    lib.tn_kernel_cgemm_noalloc_max_scratch.restype = ctypes.c_size_t
     lib.tn_last_error.argtypes = []
     lib.tn_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -223,6 +228,19 @@ def tn_kernel_cgemm(A, B, C, M, N, K, transA=0, transB=0, nbatch=1, nb=1, sAb=0,
     _check(load_library().tn_kernel_cgemm(A, B, C, M, N, K, transA, transB, nbatch, nb, sAb,
                                           sBb, sCb, sAi, sBi, sCi, precision, scratch,
                                           scratch_bytes, stream))
+
+
+def tn_kernel_cgemm_noalloc(A, B, C, M, N, K, transA=0, transB=0, nbatch=1, nb=1, sAb=0,
+                            sBb=0, sCb=0, sAi=0, sBi=0, sCi=0, precision=TN_FP32_4M,
+                            stream=None):
+    """tn_kernel_cgemm with the library's own scratch array (allocates nothing)."""
+    _check(load_library().tn_kernel_cgemm_noalloc(A, B, C, M, N, K, transA, transB, nbatch, nb,
+                                                  sAb, sBb, sCb, sAi, sBi, sCi, precision,
+                                                  stream))
+
+
+def tn_kernel_cgemm_noalloc_max_scratch():
+    return load_library().tn_kernel_cgemm_noalloc_max_scratch()
 
 
 def tn_kernel_permute(src, dst, rank, perm, nb=1, stream=None):

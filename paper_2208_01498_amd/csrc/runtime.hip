@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cstring>
 #include <limits>
+#include <mutex>
 
 #include "kernels.h"
 #include "tn_internal.h"
@@ -669,6 +670,65 @@ int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N,
     tn_ctx* none = nullptr;
     HIPCHK(none, launch_gemm(g, precision, static_cast<hipStream_t>(hip_stream)));
     return TN_OK;
+}
+
+// Scratch of tn_kernel_cgemm_noalloc: one array per GPU, reserved when the
+// library's code object is loaded on that GPU and held until the process
+// ends.  Host code never uses the symbol itself (its host-side name is not a
+// device address): the address comes from hipGetSymbolAddress, looked up once
+// per device with that device current.
+static constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocScratchBytes];
+static constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static void* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+static int noalloc_scratch_ptr(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error(std::string("HIP error: ") + hipGetErrorString(e) + " at hipGetDevice");
+        return TN_EDEVICE;
+    }
+    if (dev < 0 || dev >= kNoAllocMaxDevices) { set_error("device index out of range"); return TN_EINVAL; }
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("HIP error: ") + hipGetErrorString(e) + " at hipGetSymbolAddress");
+            return TN_EDEVICE;
+        }
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return TN_OK;
+}
+
+size_t tn_kernel_cgemm_noalloc_max_scratch(void) { return kNoAllocScratchBytes; }
+
+int tn_kernel_cgemm_noalloc(const void* A, const void* B, void* C, int32_t M, int32_t N, int32_t K,
+                            int32_t transA, int32_t transB, int32_t nbatch, int32_t nb,
+                            int64_t sAb, int64_t sBb, int64_t sCb, int64_t sAi, int64_t sBi,
+                            int64_t sCi, int32_t precision, void* hip_stream) {
+    if (!A || !B || !C || !pow2(M) || !pow2(N) || !pow2(K) || nbatch <= 0 || nb <= 0) {
+        set_error("bad gemm arguments (M, N, K must be powers of two)");
+        return TN_EINVAL;
+    }
+    if (!precision_ok(precision)) { set_error("precision mode not available"); return TN_EINVAL; }
+    const size_t part = gemm_scratch_elems(M, N, K, nbatch, nb) ? cgemm_partial_bytes(M, N, K, nbatch, nb) : 0;
+    const size_t words = precision == TN_SPLIT_FP16 ? gemm_scale_words(M, N, K, nbatch, nb) : 0;
+    const size_t need = part + words * 4;
+    if (need > kNoAllocScratchBytes) {
+        set_error("gemm needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                  std::to_string(kNoAllocScratchBytes) + " of the library's array");
+        return TN_EINVAL;
+    }
+    void* ptr = nullptr;
+    const int rc = noalloc_scratch_ptr(&ptr);
+    if (rc) return rc;
+    return tn_kernel_cgemm(A, B, C, M, N, K, transA, transB, nbatch, nb, sAb, sBb, sCb, sAi, sBi,
+                           sCi, precision, ptr, kNoAllocScratchBytes, hip_stream);
 }
 
 int tn_kernel_permute(const void* src, void* dst, int32_t rank, const int32_t* perm, int32_t nb,
