@@ -130,6 +130,57 @@ def cpu_baseline(circ, word, seconds=20.0, width=24, seed=0):
                       "slice count" % (done, len(labels), el)}
 
 
+def _serving_plan(item):
+    from paper_2208_01498_amd.planner.plan import make_plan
+    _, c, ns = item
+    return make_plan(c, n_slices=ns, B=32)
+
+
+def serving_plans(pool):
+    """The pool's plans (deterministic: seeded hierarchies), built in
+    parallel worker processes before the GPU is touched."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    with ProcessPoolExecutor(max_workers=min(len(pool), 12),
+                             mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(_serving_plan, pool))
+
+
+def serve_check(args, pool, plans):
+    """Second half of the alone-versus-mixed check for the requests a served
+    run wrote out (--serve-dump): the same bitstrings, run alone on the same
+    plans (one call per plan), must give bitwise the served amplitudes."""
+    import numpy as np
+    from paper_2208_01498_amd import binding as B
+    dump = json.load(open(args.serve_check))
+    prec = B.PRECISIONS[dump["precision"]]
+    import torch
+    free, _ = torch.cuda.mem_get_info(0)
+    eng = B.Engine(0, arena_bytes=int(free - (8 << 30)))
+    hs = {}
+    mismatched = checked = 0
+    by_plan = {}
+    for r in dump["requests"]:
+        by_plan.setdefault(r["plan"], []).append(r)
+    for k, rs in sorted(by_plan.items()):
+        if k not in hs:
+            hs[k] = eng.load(plans[k].to_blob())
+        allw = np.array([int(w) for r in rs for w in r["bitstrings"]], dtype=np.uint64)
+        alone = eng.amplitudes(hs[k], allw, prec)
+        pos = 0
+        for r in rs:
+            served = np.array(r["re"]) + 1j * np.array(r["im"])
+            n = len(served)
+            mismatched += not np.array_equal(alone[pos:pos + n], served)
+            checked += 1
+            pos += n
+        log("plan %d (%s): %d served requests rerun alone" % (k, pool[k][0], len(rs)))
+    print(json.dumps({"metric": "served results rerun alone", "checked": checked,
+                      "mismatched": mismatched, "families": sorted(set(pool[k][0] for k in by_plan)),
+                      "precision": dump["precision"]}), flush=True)
+    eng.close()
+
+
 def serve_bench(args):
     """The served mixed stream: requests drawn uniformly from four circuit
     families (three instances each, all plans resident), 1..64 bitstrings
@@ -145,8 +196,10 @@ def serve_bench(args):
     pool = serving_pool()
     prec = B.PRECISIONS[args.precision]
     t = time.perf_counter()
-    plans = [make_plan(c, n_slices=ns, B=32) for _, c, ns in pool]
+    plans = serving_plans(pool)
     log("%d plans built in %.1f s" % (len(plans), time.perf_counter() - t))
+    if args.serve_check:
+        return serve_check(args, pool, plans)
     free, _ = torch.cuda.mem_get_info(0)
     eng = B.Engine(0, arena_bytes=int(free - (8 << 30)))
     B.tn_server_config(eng.ctx, args.slots, 64)
@@ -213,8 +266,16 @@ def serve_bench(args):
     # depend on the batch or chunk it runs in)
     same = True
     mismatched = 0
+    dumped = []
     for k in sorted(set(k for k, _ in reqs)):
         js = [j for j, (kk, _) in enumerate(reqs) if kk == k]
+        if args.serve_dump and pool[k][0] in args.serve_dump_families:
+            # rerun alone in a later process (--serve-check on the dump)
+            for j in js:
+                a = done[j][0]
+                dumped.append({"request": j, "plan": k, "bitstrings": [str(int(x)) for x in reqs[j][1]],
+                               "re": a.real.tolist(), "im": a.imag.tolist()})
+            continue
         allw = np.concatenate([reqs[j][1] for j in js])
         alone = eng.amplitudes(hs[k], allw, prec)
         pos = 0
@@ -226,6 +287,9 @@ def serve_bench(args):
             pos += nb_j
         log("plan %d (%s): %d requests, %d bitstrings checked against the alone run"
             % (k, pool[k][0], len(js), len(allw)))
+    if args.serve_dump:
+        json.dump({"precision": args.precision, "requests": dumped}, open(args.serve_dump, "w"))
+        log("%d served results written to %s for the alone check" % (len(dumped), args.serve_dump))
     per_fam = {}
     for j, (k, w) in enumerate(reqs):
         per_fam.setdefault(pool[k][0], []).append(lat[j])
@@ -235,8 +299,8 @@ def serve_bench(args):
            "lambda_req_per_s": lam, "saturation_req_per_s": sat, "load": args.serve_load,
            "n_requests": len(reqs), "cap_s": cap, "slots": args.slots,
            "max_heavy": args.max_heavy,
-           "alone_equals_mixed": same, "checked_against_alone": len(reqs),
-           "mismatched": mismatched,
+           "alone_equals_mixed": same, "checked_against_alone": len(reqs) - len(dumped),
+           "written_for_alone_check": len(dumped), "mismatched": mismatched,
            "precision": args.precision,
            "seconds_per_bitstring_alone": per_b,
            "p50_by_family": {f: float(np.percentile(v, 50)) for f, v in per_fam.items()},
@@ -321,10 +385,16 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="arrival rate as a fraction of the saturation rate")
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--max-heavy", type=int, default=2,
+    ap.add_argument("--max-heavy", type=int, default=1,
                     help="served batches of at least 1e14 flops running at once")
     ap.add_argument("--serve-cap-s", type=float, default=600.0,
                     help="submit only requests arriving within this many seconds (0: all)")
+    ap.add_argument("--serve-dump", default=None,
+                    help="write the served results of --serve-dump-families here instead of "
+                         "rerunning them alone in this process")
+    ap.add_argument("--serve-dump-families", nargs="*", default=["8x8d16"])
+    ap.add_argument("--serve-check", default=None,
+                    help="rerun the requests of a --serve-dump file alone and compare bitwise")
     ap.add_argument("--paper-families", action="store_true",
                     help="the paper's IQP and Sycamore-type families at L = 4..8 instead")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -335,7 +405,7 @@ def main():
               "(slices would shard across GPUs with one all-reduce of the FP64 sums)",
               file=sys.stderr)
         sys.exit(2)
-    if args.serve:
+    if args.serve or args.serve_check:
         return serve_bench(args)
     if args.copy_calibration:
         return copy_calibration()
