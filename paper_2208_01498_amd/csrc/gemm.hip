@@ -128,21 +128,33 @@ struct Smem {
     // reads its MFMA operand with one 4-byte load and no select
     static constexpr int PA = BM + 2;
     static constexpr int PB = BN + 1;            // in 16-byte units
-    // bf16: A as [m][2*KT real], B as [2*BN real cols][2*KT real rows]
-    static constexpr int RA = 2 * KT + 8;
+    // 16-bit halves: rows of KT words (one 4-byte word per complex k, its
+    // two 16-bit reals) at a stride of RW = KT + 1 words (odd: rows whose
+    // indices differ mod 32 start in different banks).  A row m sits at
+    // row (m mod 2) GA + m / 2 and real column r of B at (r mod 4) GB + r / 4,
+    // so the rows one store instruction writes (every second A row when m
+    // is the contiguous index, every fourth B column) are consecutive, and
+    // the 32 consecutive rows a half-wave reads stay 32 apart mod 32
+    static constexpr int RW = KT + 1;
+    static constexpr int GA = BM / 2 + 16;
+    static constexpr int GB = BN / 2 + 8;
+    static constexpr int RAh = GA + BM / 2;            // rows per A plane
+    static constexpr int RBh = 3 * GB + BN / 2;        // rows per B plane
     static constexpr size_t bytes_fp32 = 2 * (size_t)KT * (PA * 8 + PB * 16);
-    static constexpr size_t bytes_bf16 = 2 * (size_t)(2 * BM * RA + 2 * 2 * BN * RA) * 2;
+    static constexpr size_t bytes_bf16 = 2 * (size_t)(RAh + RBh) * RW * 4 * 2;
     static constexpr size_t bytes = PREC == 0 ? bytes_fp32 : bytes_bf16;
 };
 
 }  // namespace
 
 template <int PREC, int WGM, int WGN, int WMF, int WNF, bool TA, bool TB>
-__global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
+__global__ void __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(4)))
+k_cgemm(GemmArgs g) {
     using S = Smem<PREC, WGM, WGN, WMF, WNF>;
     constexpr int KT = S::KT;
     constexpr int NT = 64 * WGM * WGN;
-    constexpr int BM = S::BM, BN = S::BN, PA = S::PA, PB = S::PB, RA = S::RA;
+    constexpr int BM = S::BM, BN = S::BN, PA = S::PA, PB = S::PB, RW = S::RW;
+    constexpr int GA = S::GA, GB = S::GB, RAh = S::RAh, RBh = S::RBh;
     constexpr int FA = BM * KT / 2;      // float4 (2 complex) loads per A tile
     constexpr int FB = KT * BN / 2;
     constexpr int LA = (FA + NT - 1) / NT;
@@ -285,10 +297,13 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
     float2* As = reinterpret_cast<float2*>(smem);              // [2][KT][PA]
     float4* Bs = reinterpret_cast<float4*>(As + 2 * KT * PA);  // [2][KT][PB]
     // ---------------------------------------------------------------- bf16
-    __bf16* Ah = reinterpret_cast<__bf16*>(smem);               // [2][BM][RA]
-    __bf16* Al = Ah + 2 * BM * RA;
-    __bf16* Bh = Al + 2 * BM * RA;                               // [2][2BN][RA]
-    __bf16* Bl = Bh + 2 * 2 * BN * RA;
+    uint32_t* Ah = reinterpret_cast<uint32_t*>(smem);           // [2][RAh][RW] words
+    uint32_t* Al = Ah + 2 * RAh * RW;
+    uint32_t* Bh = Al + 2 * RAh * RW;                            // [2][RBh][RW]
+    uint32_t* Bl = Bh + 2 * RBh * RW;
+    // word w (complex k) of A row m / B real column r
+    auto wa = [](int m, int w) { return ((m & 1) * GA + (m >> 1)) * RW + w; };
+    auto wb = [](int r, int w) { return ((r & 3) * GB + (r >> 2)) * RW + w; };
 
     // two floats (one complex, both times the scale sc of its row or
     // column in fp16 mode) -> packed 16-bit pairs (hi, lo), x = hi + lo; the
@@ -329,14 +344,14 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
                     a[k2 * PA + m2] = make_float2(ra[i].z, ra[i].w);
                 }
             } else {
-                uint32_t* ah = reinterpret_cast<uint32_t*>(Ah + buf * BM * RA);
-                uint32_t* al = reinterpret_cast<uint32_t*>(Al + buf * BM * RA);
+                uint32_t* ah = Ah + buf * RAh * RW;
+                uint32_t* al = Al + buf * RAh * RW;
                 uint32_t h0, l0, h1, l1;
                 split2(ra[i].x, ra[i].y, sca[i][0], h0, l0);
                 split2(ra[i].z, ra[i].w, sca[i][1], h1, l1);
                 // real index 2k + (re, im) of row m: one 4-byte word per complex
-                ah[(m * RA + 2 * k) / 2] = h0; al[(m * RA + 2 * k) / 2] = l0;
-                ah[(m2 * RA + 2 * k2) / 2] = h1; al[(m2 * RA + 2 * k2) / 2] = l1;
+                ah[wa(m, k)] = h0; al[wa(m, k)] = l0;
+                ah[wa(m2, k2)] = h1; al[wa(m2, k2)] = l1;
             }
         }
 #pragma unroll
@@ -351,8 +366,8 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
                 b[k * PB + n] = make_float4(rb[i].x, rb[i].y, -rb[i].y, rb[i].x);
                 b[k2 * PB + n2] = make_float4(rb[i].z, rb[i].w, -rb[i].w, rb[i].z);
             } else {
-                uint32_t* bh = reinterpret_cast<uint32_t*>(Bh + buf * 2 * BN * RA);
-                uint32_t* bl = reinterpret_cast<uint32_t*>(Bl + buf * 2 * BN * RA);
+                uint32_t* bh = Bh + buf * RBh * RW;
+                uint32_t* bl = Bl + buf * RBh * RW;
                 // real column 2n: rows (2k, 2k+1) = (Br, -Bi); column 2n+1:
                 // (Bi, Br).  Each real is split once; the negated halves of
                 // -Bi are the halves of Bi with the sign bit flipped (exact)
@@ -365,10 +380,10 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
                 auto swap = [](uint32_t v) {             // (r, i) -> (i, r)
                     return (v >> 16) | (v << 16);
                 };
-                bh[((2 * n) * RA + 2 * k) / 2] = neg_hi(h0); bl[((2 * n) * RA + 2 * k) / 2] = neg_hi(l0);
-                bh[((2 * n + 1) * RA + 2 * k) / 2] = swap(h0); bl[((2 * n + 1) * RA + 2 * k) / 2] = swap(l0);
-                bh[((2 * n2) * RA + 2 * k2) / 2] = neg_hi(h1); bl[((2 * n2) * RA + 2 * k2) / 2] = neg_hi(l1);
-                bh[((2 * n2 + 1) * RA + 2 * k2) / 2] = swap(h1); bl[((2 * n2 + 1) * RA + 2 * k2) / 2] = swap(l1);
+                bh[wb(2 * n, k)] = neg_hi(h0); bl[wb(2 * n, k)] = neg_hi(l0);
+                bh[wb(2 * n + 1, k)] = swap(h0); bl[wb(2 * n + 1, k)] = swap(l0);
+                bh[wb(2 * n2, k2)] = neg_hi(h1); bl[wb(2 * n2, k2)] = neg_hi(l1);
+                bh[wb(2 * n2 + 1, k2)] = swap(h1); bl[wb(2 * n2 + 1, k2)] = swap(l1);
             }
         }
     };
@@ -402,24 +417,33 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_cgemm(GemmArgs g) {
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk & 1][i], bv[kk & 1][j], acc[i][j], 0, 0, 0);
             }
         } else {
-            const __bf16* ah = Ah + buf * BM * RA;
-            const __bf16* al = Al + buf * BM * RA;
-            const __bf16* bh = Bh + buf * 2 * BN * RA;
-            const __bf16* bl = Bl + buf * 2 * BN * RA;
+            const uint32_t* ah = Ah + buf * RAh * RW;
+            const uint32_t* al = Al + buf * RAh * RW;
+            const uint32_t* bh = Bh + buf * RBh * RW;
+            const uint32_t* bl = Bl + buf * RBh * RW;
+            // the 8 reals k = 8 half .. 8 half + 7 of a 16-k MFMA step are the
+            // four words 4 half .. 4 half + 3 of the row: four 4-byte reads
+            // at constant offsets from one lane address
+            auto rd8 = [&](const uint32_t* row) {
+                uint32_t v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = row[q];
+                return __builtin_bit_cast(bf16x8, v);
+            };
 #pragma unroll
             for (int kc = 0; kc < KT / 8; ++kc) {
                 bf16x8 xh[WMF], xl[WMF], yh[WNF], yl[WNF];
 #pragma unroll
                 for (int i = 0; i < WMF; ++i) {
-                    const int m = wm + i * 32 + l32;
-                    xh[i] = *reinterpret_cast<const bf16x8*>(ah + m * RA + 16 * kc + 8 * half);
-                    xl[i] = *reinterpret_cast<const bf16x8*>(al + m * RA + 16 * kc + 8 * half);
+                    const int o = wa(wm + i * 32 + l32, 8 * kc + 4 * half);
+                    xh[i] = rd8(ah + o);
+                    xl[i] = rd8(al + o);
                 }
 #pragma unroll
                 for (int j = 0; j < WNF; ++j) {
-                    const int col = 2 * (wn + j * 16) + l32;
-                    yh[j] = *reinterpret_cast<const bf16x8*>(bh + col * RA + 16 * kc + 8 * half);
-                    yl[j] = *reinterpret_cast<const bf16x8*>(bl + col * RA + 16 * kc + 8 * half);
+                    const int o = wb(2 * (wn + j * 16) + l32, 8 * kc + 4 * half);
+                    yh[j] = rd8(bh + o);
+                    yl[j] = rd8(bl + o);
                 }
 #pragma unroll
                 for (int i = 0; i < WMF; ++i)
