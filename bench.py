@@ -463,9 +463,9 @@ def main():
     kinds = B.KERNEL_CLASSES
     per_kind = {kinds[i]: {"launches": prof["launches"][i], "ms": prof["time_ms"][i],
                            "flops": prof["flops"][i], "bytes": prof["bytes"][i]}
-                for i in range(6)}
+                for i in range(len(kinds))}
     log("per kernel class", json.dumps(per_kind))
-    dom = max(range(4), key=lambda i: prof["time_ms"][i])
+    dom = max(B.GEMM_CLASSES, key=lambda i: prof["time_ms"][i])
     ms = prof["time_ms"][dom]
     alg = prof["flops"][dom] / (ms * 1e-3) if ms > 0 else 0.0
     achieved = alg * EXEC[args.precision]
@@ -476,7 +476,7 @@ def main():
                 "flops_per_launch": prof["flops"][dom] * EXEC[args.precision] / max(1, prof["launches"][dom]),
                 "algorithmic_tflops": alg / 1e12,
                 "avg_launch_ms": ms / max(1, prof["launches"][dom]),
-                "gemm_time_frac": sum(prof["time_ms"][:4]) / max(1e-9, sum(prof["time_ms"]))}
+                "gemm_time_frac": sum(prof["time_ms"][i] for i in B.GEMM_CLASSES) / max(1e-9, sum(prof["time_ms"]))}
     # the permute kernels against HBM (algorithmic bytes: one read and one
     # write of every element)
     pm = prof["time_ms"][4]

@@ -190,15 +190,17 @@ typedef struct tn_exec_stats {
     double permute_bytes;             /* 16 bytes per permuted element */
     /* per kernel class (0 dot-product GEMM for tiny outputs, 1 MFMA GEMM
      * 64x64 tile, 2 MFMA GEMM 128x128 tile, 3 MFMA GEMM 128x16 tile, 4
-     * permute, 5 leaf gather): launches, summed device time from HIP events
+     * permute, 5 leaf gather, 6 MFMA GEMM one wave per 32x32 block for
+     * products of at most 4096 outputs per batch entry): launches, summed
+     * device time from HIP events
      * recorded around each launch on the executing stream (only when
      * profiling is on), algorithmic flops (GEMM: 8 per complex multiply-add)
      * and algorithmic bytes (GEMM: operands read once and C written once;
      * permute: 16 per element; gather: 8 per written element) */
-    int64_t launches[6];
-    double time_ms[6];
-    double flops[6];
-    double bytes[6];
+    int64_t launches[7];
+    double time_ms[7];
+    double flops[7];
+    double bytes[7];
 } tn_exec_stats;
 
 /* Turn per-launch event timing of tn_contract_amplitudes on (1) or off (0).
@@ -256,8 +258,10 @@ int tn_kernel_cgemm(const void* A, const void* B, void* C, int32_t M, int32_t N,
 size_t tn_kernel_cgemm_scratch_bytes(int32_t M, int32_t N, int32_t K, int32_t nbatch, int32_t nb);
 /* How tn_kernel_cgemm (and every plan step of this shape) sums over k, host
  * only: *kind is the kernel class (0: K-parallel dot product for M*N <= 16,
- * summed in float64; 1, 2, 3: MFMA tiles of 64x64, 128x128, 128x16 class,
- * each output element accumulated in FP32 over its K range); *splits is the
+ * summed in float64; 1, 2, 3: MFMA tiles of 64x64, 128x128, 128x16 class;
+ * 6: one wave per 32x32 block for M*N <= 4096, K <= 256 and one K range
+ * in the FP32 modes (the split modes take the 128x16 tile there); every MFMA class
+ * accumulates each output element in FP32 over its K range); *splits is the
  * number of K ranges of K/splits consecutive k (split-K), whose partial sums
  * are added in float64 in range order.  The summation order fixes the
  * rounding error of a step: the accumulation of one element rounds K/splits

@@ -55,12 +55,13 @@ class tn_exec_stats(ctypes.Structure):
                 ("steps_reused", ctypes.c_int64), ("chunk", ctypes.c_int32),
                 ("n_chunks", ctypes.c_int32), ("slice_block", ctypes.c_int32),
                 ("graph_replays", ctypes.c_int32), ("algorithmic_flops", ctypes.c_double),
-                ("permute_bytes", ctypes.c_double), ("launches", ctypes.c_int64 * 6),
-                ("time_ms", ctypes.c_double * 6), ("flops", ctypes.c_double * 6),
-                ("bytes", ctypes.c_double * 6)]
+                ("permute_bytes", ctypes.c_double), ("launches", ctypes.c_int64 * 7),
+                ("time_ms", ctypes.c_double * 7), ("flops", ctypes.c_double * 7),
+                ("bytes", ctypes.c_double * 7)]
 
 KERNEL_CLASSES = ["cgemm_dot", "cgemm_mfma_64x64", "cgemm_mfma_128x128", "cgemm_mfma_128x16",
-                  "permute", "gather"]
+                  "permute", "gather", "cgemm_wave_32x32"]
+GEMM_CLASSES = [0, 1, 2, 3, 6]
 
 
 _lib = None

@@ -821,17 +821,142 @@ k_cgemm3m(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
-// Tiny outputs (M*N <= 16), any K: each workgroup sums one K range of one
-// batch entry; the 256 lanes are split into M*N groups of L = 256/(M*N)
-// consecutive lanes, one output per group, lanes striding along k, followed
-// by an LDS tree reduction within each group (fixed order).  The products
-// of the FP32 operands are exact in float64, and the lane sums and the tree
-// run in float64: the only FP32 rounding is the final store (and the
-// float64 partials of a split K are summed by k_reduce_splitk before it).
+// Small products (at most 64 x 64 outputs per batch entry, K <= 256, one K
+// range), FP32 4M and 3M:
+// one wave per 32 x 32 complex output block of one batch entry, four waves
+// per workgroup, operands read straight from global memory (a batch entry's
+// operands are a few KiB) with no LDS and no barrier.  Each output element
+// sees the same MFMA sequence over k as in k_cgemm / k_cgemm3m (two k per
+// step for 3M, one complex k per step for 4M, from k = 0 up), so the
+// results are bitwise those of the tile kernels; the kernel only packs the
+// many tiny batch entries that leave a 128 x 32 tile mostly empty.
+template <int PREC, bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_cgemm_wave(GemmArgs g) {
+    const int Mt = gemm_rows(g);
+    const int Nt = gemm_cols(g);
+    const int lgM = __builtin_ctz((unsigned)g.M), lgN = __builtin_ctz((unsigned)g.N);
+    const int bm = (Mt + 31) / 32, bnb = (Nt + 31) / 32;
+    const size_t nblk = (size_t)bm * bnb;
+    const size_t n_outer = g.fold == 0 ? (size_t)g.nr * g.nb : (size_t)g.nb;
+    const size_t wid = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wid >= nblk * g.nbatch * n_outer) return;          // whole wave exits
+    size_t blk = wid;
+    const size_t tile = blk % nblk;
+    blk /= nblk;
+    const size_t ib = blk % g.nbatch;
+    blk /= g.nbatch;
+    const size_t bb = blk % g.nb;
+    const size_t rr = g.fold == 0 ? blk / g.nb : 0;
+    const int m0 = (int)(tile % bm) * 32, n0 = (int)(tile / bm) * 32;
+    const float2* A = g.A + bb * g.sAb + ib * g.sAi + pext_u(rr, g.mA) * g.sAr;
+    const float2* B = g.B + bb * g.sBb + ib * g.sBi + pext_u(rr, g.mB) * g.sBr;
+    const long long sAf = (g.fold == 2 || g.fold == 3) ? g.sAr : 0;
+    const long long sBf = (g.fold == 1 || g.fold == 3) ? g.sBr : 0;
+    const int lane = threadIdx.x & 63;
+    const int half = lane >> 5;
+    const int l32 = lane & 31;
+    const int K = g.K;
+    auto ldA = [&](int mp, int k) -> float2 {
+        if (mp >= Mt || k >= K) return make_float2(0.f, 0.f);
+        const int m = mp & (g.M - 1);
+        return A[(size_t)(mp >> lgM) * sAf + (TA ? (size_t)k * g.M + m : (size_t)m * K + k)];
+    };
+    auto ldB = [&](int k, int np) -> float2 {
+        if (np >= Nt || k >= K) return make_float2(0.f, 0.f);
+        const int n = np & (g.N - 1);
+        return B[(size_t)(np >> lgN) * sBf + (TB ? (size_t)n * K + k : (size_t)k * g.N + n)];
+    };
+    float2* Cb = g.C + bb * g.sCb + ib * g.sCi + rr * g.sCr;
+    if constexpr (PREC == 1) {
+        // 3M: lane (half, l32) holds A[m0 + l32][k] and B[k][n0 + l32] for
+        // k = 2 ks + half; P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi)
+        floatx16 acc[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[p][r] = 0.f;
+        const int nks = (K + 1) / 2;
+        float2 a = ldA(m0 + l32, half), b = ldB(half, n0 + l32);
+        for (int ks = 0; ks < nks; ++ks) {
+            const float2 an = ldA(m0 + l32, 2 * ks + 2 + half), bn = ldB(2 * ks + 2 + half, n0 + l32);
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc[1], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x + a.y, b.x + b.y, acc[2], 0, 0, 0);
+            a = an;
+            b = bn;
+        }
+        // acc[p][r]: row 8 (r/4) + 4 half + r % 4, column l32
+        const int np = n0 + l32;
+        if (np >= Nt) return;
+        const int n = np & (g.N - 1);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int mp = m0 + 8 * (r >> 2) + 4 * half + (r & 3);
+            if (mp >= Mt) continue;
+            const int m = mp & (g.M - 1);
+            const size_t e = (size_t)gemm_c_copy(g, (unsigned)(mp >> lgM), (unsigned)(np >> lgN)) +
+                             gemm_c_elem(g, m, n);
+            const float p1 = acc[0][r], p2 = acc[1][r], p3 = acc[2][r];
+            Cb[e] = make_float2(p1 - p2, p3 - p1 - p2);
+        }
+    } else {
+        // 4M: one complex k per step; lane (half, l32) holds component half
+        // of A[m0 + l32][k] and entry 2 half + (l32 & 1) of the expanded
+        // 2 x 2 block [[Br, Bi], [-Bi, Br]] of B[k][n0 + 16 j + l32 / 2]
+        floatx16 acc[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
+        auto bop = [&](float2 v) {
+            return half == 0 ? ((l32 & 1) ? v.y : v.x) : ((l32 & 1) ? v.x : -v.y);
+        };
+        float2 a = ldA(m0 + l32, 0);
+        float2 b0 = ldB(0, n0 + (l32 >> 1)), b1 = ldB(0, n0 + 16 + (l32 >> 1));
+        for (int k = 0; k < K; ++k) {
+            const float2 an = ldA(m0 + l32, k + 1);
+            const float2 bn0 = ldB(k + 1, n0 + (l32 >> 1)), bn1 = ldB(k + 1, n0 + 16 + (l32 >> 1));
+            const float av = half ? a.y : a.x;
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bop(b0), acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bop(b1), acc[1], 0, 0, 0);
+            a = an;
+            b0 = bn0;
+            b1 = bn1;
+        }
+        // acc[j][r]: real row 8 (r/4) + 4 half + r % 4, real column l32 =
+        // component l32 & 1 of complex column 16 j + l32 / 2
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int np = n0 + 16 * j + (l32 >> 1);
+            if (np >= Nt) continue;
+            const int n = np & (g.N - 1);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int mp = m0 + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (mp >= Mt) continue;
+                const int m = mp & (g.M - 1);
+                const size_t e = (size_t)gemm_c_copy(g, (unsigned)(mp >> lgM), (unsigned)(np >> lgN)) +
+                                 gemm_c_elem(g, m, n);
+                reinterpret_cast<float*>(Cb + e)[l32 & 1] = acc[j][r];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tiny outputs (M*N <= 16), any K: each wave sums one K range of one batch
+// entry (four waves per workgroup, no LDS); its 64 lanes are split into
+// M*N groups of L = 64/(M*N) consecutive lanes, one output per group, lanes
+// striding along k, then a butterfly over the group's lanes (fixed order).
+// The products of the FP32 operands are exact in float64, and the lane sums
+// and the butterfly run in float64: the only FP32 rounding is the final
+// store (and the float64 partials of a split K are summed by
+// k_reduce_splitk before it).
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_cgemm_dot(GemmArgs g) {
-    __shared__ double2 red[256];
-    size_t blk = blockIdx.x;
+    const size_t n_outer = (size_t)g.nr * g.nb;
+    size_t blk = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (blk >= (size_t)g.splits * g.nbatch * n_outer) return;   // whole wave exits
     const int split = (int)(blk % g.splits);
     blk /= g.splits;
     const size_t ib = blk % g.nbatch;
@@ -839,15 +964,14 @@ __global__ void __launch_bounds__(256) k_cgemm_dot(GemmArgs g) {
     const size_t bb = blk % g.nb;
     const size_t rr = blk / g.nb;                    // slice block as an outer batch
     const size_t outer = rr * g.nb + bb;
-    const size_t n_outer = (size_t)g.nr * g.nb;
     const int kper = g.K / g.splits;
     const int kb = split * kper, ke = kb + kper;
     const float2* A = g.A + bb * g.sAb + ib * g.sAi + pext_u(rr, g.mA) * g.sAr;
     const float2* B = g.B + bb * g.sBb + ib * g.sBi + pext_u(rr, g.mB) * g.sBr;
     const int M = g.M, N = g.N, MN = M * N;
-    const int L = 256 / MN;
-    const int tid = threadIdx.x;
-    const int o = tid / L, kl = tid % L;
+    const int L = 64 / MN;
+    const int lane = threadIdx.x & 63;
+    const int o = lane / L, kl = lane % L;
     const int m = o / N, n = o % N;
     double cr = 0.0, ci = 0.0;
     for (int k = kb + kl; k < ke; k += L) {
@@ -858,22 +982,16 @@ __global__ void __launch_bounds__(256) k_cgemm_dot(GemmArgs g) {
         ci = fma((double)a.x, (double)b.y, ci);
         ci = fma((double)a.y, (double)b.x, ci);
     }
-    red[tid] = make_double2(cr, ci);
-    __syncthreads();
     for (int w = L / 2; w > 0; w >>= 1) {
-        if (kl < w) {
-            red[tid].x += red[tid + w].x;
-            red[tid].y += red[tid + w].y;
-        }
-        __syncthreads();
+        cr += __shfl_xor(cr, w);
+        ci += __shfl_xor(ci, w);
     }
     if (kl == 0) {
-        const double2 v = red[tid];
         if (g.splits > 1) {
-            g.Pd[(((size_t)split * n_outer + outer) * g.nbatch + ib) * (size_t)MN + o] = v;
+            g.Pd[(((size_t)split * n_outer + outer) * g.nbatch + ib) * (size_t)MN + o] = make_double2(cr, ci);
         } else {
             float2* C = g.C + bb * g.sCb + ib * g.sCi + rr * g.sCr;
-            C[gemm_c_elem(g, m, n)] = make_float2((float)v.x, (float)v.y);
+            C[gemm_c_elem(g, m, n)] = make_float2((float)cr, (float)ci);
         }
     }
 }
@@ -1039,6 +1157,11 @@ GemmChoice choose_gemm(int M, int N, int K, int nbatch, int Mt, int Nt) {
     if (m >= 128 && n >= 128) c.kind = GEMM_MFMA_128x128;
     else if (m >= 64 && n >= 64) c.kind = GEMM_MFMA_64x64;
     else c.kind = GEMM_MFMA_128x16;
+    // small products of one K range (at most 64 x 64 outputs per batch
+    // entry, K <= 256): one wave per 32 x 32 block (FP32 modes; the same
+    // MFMA sequence per element as the tile kernels).  Decided from the
+    // unfolded shape, like everything else here.
+    if (c.splits == 1 && (long long)M * N <= 4096 && K <= 256) c.kind = GEMM_WAVE;
     return c;
 }
 
@@ -1146,12 +1269,13 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
     const size_t n_outer = g.fold == 0 ? (size_t)g.nr * g.nb : (size_t)g.nb;
     const size_t batches = (size_t)g.nbatch * n_outer * c.splits;
     if (c.kind == GEMM_DOT) {
+        const unsigned grid = (unsigned)((batches + 3) / 4);     // one wave per batch entry and K range
         if (g.transA) {
-            if (g.transB) hipLaunchKernelGGL((k_cgemm_dot<true, true>), dim3((unsigned)batches), dim3(256), 0, s, g);
-            else hipLaunchKernelGGL((k_cgemm_dot<true, false>), dim3((unsigned)batches), dim3(256), 0, s, g);
+            if (g.transB) hipLaunchKernelGGL((k_cgemm_dot<true, true>), dim3(grid), dim3(256), 0, s, g);
+            else hipLaunchKernelGGL((k_cgemm_dot<true, false>), dim3(grid), dim3(256), 0, s, g);
         } else {
-            if (g.transB) hipLaunchKernelGGL((k_cgemm_dot<false, true>), dim3((unsigned)batches), dim3(256), 0, s, g);
-            else hipLaunchKernelGGL((k_cgemm_dot<false, false>), dim3((unsigned)batches), dim3(256), 0, s, g);
+            if (g.transB) hipLaunchKernelGGL((k_cgemm_dot<false, true>), dim3(grid), dim3(256), 0, s, g);
+            else hipLaunchKernelGGL((k_cgemm_dot<false, false>), dim3(grid), dim3(256), 0, s, g);
         }
     } else {
         if (precision == 3) {
@@ -1185,6 +1309,29 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
                 }
             }
         }
+        if (c.kind == GEMM_WAVE && (precision == 0 || precision == 1)) {
+            const size_t waves = (size_t)((Mt + 31) / 32) * ((Nt + 31) / 32) * g.nbatch * n_outer;
+            const unsigned grid = (unsigned)((waves + 3) / 4);
+            if (precision == 1) {
+                if (g.transA) {
+                    if (g.transB) hipLaunchKernelGGL((k_cgemm_wave<1, true, true>), dim3(grid), dim3(256), 0, s, g);
+                    else hipLaunchKernelGGL((k_cgemm_wave<1, true, false>), dim3(grid), dim3(256), 0, s, g);
+                } else {
+                    if (g.transB) hipLaunchKernelGGL((k_cgemm_wave<1, false, true>), dim3(grid), dim3(256), 0, s, g);
+                    else hipLaunchKernelGGL((k_cgemm_wave<1, false, false>), dim3(grid), dim3(256), 0, s, g);
+                }
+            } else {
+                if (g.transA) {
+                    if (g.transB) hipLaunchKernelGGL((k_cgemm_wave<0, true, true>), dim3(grid), dim3(256), 0, s, g);
+                    else hipLaunchKernelGGL((k_cgemm_wave<0, true, false>), dim3(grid), dim3(256), 0, s, g);
+                } else {
+                    if (g.transB) hipLaunchKernelGGL((k_cgemm_wave<0, false, true>), dim3(grid), dim3(256), 0, s, g);
+                    else hipLaunchKernelGGL((k_cgemm_wave<0, false, false>), dim3(grid), dim3(256), 0, s, g);
+                }
+            }
+            return hipGetLastError();
+        }
+        if (c.kind == GEMM_WAVE) c.kind = GEMM_MFMA_128x16;     // split modes: the tile kernel
         int bm = 128, bn = 128;
         if (c.kind == GEMM_MFMA_128x128 && precision == 1) bn = 64;
         if (c.kind == GEMM_MFMA_64x64) { bm = 64; bn = 64; }
@@ -1209,10 +1356,10 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
 }
 
 int gemm_kind(const GemmArgs& g, int precision) {
-    (void)precision;
     GemmArgs f = g;
     if (f.nr <= 1) { f.nr = 1; f.fold = 0; }
     const int Mt = gemm_rows(f);
     const int Nt = gemm_cols(f);
-    return choose_gemm(g.M, g.N, g.K, g.nbatch, Mt, Nt).kind;
+    const int k = choose_gemm(g.M, g.N, g.K, g.nbatch, Mt, Nt).kind;
+    return k == GEMM_WAVE && precision != 0 && precision != 1 ? GEMM_MFMA_128x16 : k;
 }

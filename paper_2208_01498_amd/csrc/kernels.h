@@ -102,7 +102,11 @@ __host__ __device__ inline long long gemm_c_copy(const GemmArgs& g, unsigned a, 
 
 hipError_t launch_gather(const GatherArgs& g, hipStream_t s);
 hipError_t launch_permute(const PermArgs& a, hipStream_t s);
-enum { GEMM_DOT = 0, GEMM_MFMA_64x64 = 1, GEMM_MFMA_128x128 = 2, GEMM_MFMA_128x16 = 3 };
+// kernel classes of the GEMMs (the values index the per-class statistics,
+// where 4 and 5 are the permute and gather kernels)
+enum { GEMM_DOT = 0, GEMM_MFMA_64x64 = 1, GEMM_MFMA_128x128 = 2, GEMM_MFMA_128x16 = 3,
+       GEMM_WAVE = 6 };
+constexpr int kKernelClasses = 7;
 struct GemmChoice {
     int kind;                 // GEMM_*
     int splits;               // K ranges (1 = no split-K)

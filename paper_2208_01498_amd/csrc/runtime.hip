@@ -108,7 +108,7 @@ static void add_stats(tn_exec_stats& a, const tn_exec_stats& d, int sign) {
     a.steps_reused += sign * d.steps_reused;
     a.algorithmic_flops += sign * d.algorithmic_flops;
     a.permute_bytes += sign * d.permute_bytes;
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < kKernelClasses; ++i) {
         a.launches[i] += sign * d.launches[i];
         a.flops[i] += sign * d.flops[i];
         a.bytes[i] += sign * d.bytes[i];
