@@ -74,6 +74,16 @@ def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError("libtnamp.so is not built (run paper_2208_01498_amd.build); "
                            "there is no fallback path")
+    # PyTorch ships its own HIP runtime and asks for it by a name
+    # (libamdhip64.so) that differs from the runtime's soname
+    # (libamdhip64.so.7).  Loaded after torch, the library binds to torch's
+    # runtime; loaded before, it brings in the system runtime and torch then
+    # loads a second one, and the library's runtime finds no device.  So torch,
+    # when present, is loaded first: one HIP runtime per process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, sz, i32, u64p = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)
     dp = ctypes.POINTER(ctypes.c_double)

@@ -22,6 +22,9 @@
 //   k_cgemm3m       FP32 3M on the same MFMA used as a real 32 x 32 x 2
 //                   product: three real products per complex product
 //                   (6 MNK executed flops instead of 8 MNK)
+//   k_cgemm_wave    small products (at most 64 x 64 outputs per batch
+//                   entry, K <= 256, FP32 modes): one wave per 32 x 32
+//                   block, operands straight from global memory
 //   k_cgemm_dot     tiny M*N with long K: a K-parallel dot product (every
 //                   precision mode)
 //   split-K         when a shape has too few output tiles to fill the chip,
@@ -29,14 +32,17 @@
 //                   products are summed in range order by k_reduce_splitk
 // Tiles: WGM x WGN waves per workgroup (4 or 8); a wave owns WMF x WNF
 // blocks of 32 x 16 (4M, split) or 32 x 32 (3M) complex outputs; 8 complex k
-// per stage; global loads of the next stage are issued
-// before the MFMAs of the current one and land in the other half of a
-// double-buffered LDS, one barrier per stage.
+// per stage (16 for 3M); the global loads of the next stage are issued back
+// to back before the MFMAs of the current one and land in the other half of
+// a double-buffered LDS, one barrier per stage.  Workgroups are renumbered
+// so that each XCD takes one contiguous range of tiles, walked in groups of
+// TILE_GROUP tile rows (xcd_logical, tile_rc).
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <mutex>
 
 #include "kernels.h"
@@ -52,6 +58,28 @@ constexpr int KT_SPLIT = 8;    // complex k per LDS stage, split modes (one MFMA
 constexpr int KT_FP32 = 8;     // complex k per LDS stage, FP32 (keeps two workgroups per CU)
 constexpr int KT_3M = 16;      // complex k per LDS stage, FP32 3M (two real planes per operand)
 constexpr int KT = 16;         // K granularity of the split-K ranges
+
+constexpr int TILE_GROUP = 8;  // tile rows per group in the tile order (tile_rc)
+
+// Logical index of workgroup b of n: workgroups go to the eight XCDs in
+// turn (b mod 8), each XCD with an L2 of its own; renumbered so that each
+// XCD takes one contiguous range of logical indices
+__device__ __forceinline__ size_t xcd_logical(size_t b, size_t n) {
+    const size_t x = b & 7, i = b >> 3, q = n >> 3, r = n & 7;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// Tile (tm, tn) of logical tile t: groups of TILE_GROUP tile rows, walked
+// column by column, so that the workgroups resident on one XCD at a time
+// cover a block of rows and columns and share their A and B panels in L2
+__device__ __forceinline__ void tile_rc(size_t t, int tiles_m, int tiles_n, int& tm, int& tn) {
+    const size_t per = (size_t)TILE_GROUP * tiles_n;
+    const int first = (int)(t / per) * TILE_GROUP;
+    const int gs = min(TILE_GROUP, tiles_m - first);
+    const int w = (int)(t % per);
+    tm = first + w % gs;
+    tn = w / gs;
+}
 
 // bits of x at the set positions of m, compacted (parallel bit extract)
 __device__ __forceinline__ size_t pext_u(size_t x, unsigned m) {
@@ -169,7 +197,7 @@ k_cgemm(GemmArgs g) {
     const int tiles_m = (Mt + BM - 1) / BM;
     const int tiles_n = (Nt + BN - 1) / BN;
     const size_t tiles = (size_t)tiles_m * tiles_n;
-    size_t blk = blockIdx.x;
+    size_t blk = xcd_logical(blockIdx.x, gridDim.x);
     const size_t tile = blk % tiles;
     blk /= tiles;
     const int split = (int)(blk % g.splits);
@@ -180,8 +208,8 @@ k_cgemm(GemmArgs g) {
     const size_t rr = g.fold == 0 ? blk / g.nb : 0;
     const size_t outer = g.fold == 0 ? rr * g.nb + bb : bb;
     const size_t n_outer = g.fold == 0 ? (size_t)g.nr * g.nb : (size_t)g.nb;
-    const int tm = (int)(tile % tiles_m);
-    const int tn = (int)(tile / tiles_m);
+    int tm, tn;
+    tile_rc(tile, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
     const int kper = g.K / g.splits;
     const int kb = split * kper, ke = kb + kper;
@@ -247,14 +275,17 @@ k_cgemm(GemmArgs g) {
         if (n0 + n >= Nt || k >= ke) return make_float2(0.f, 0.f);
         return B[adB(k, n0 + n)];
     };
-    auto load = [&](int k0) {
+    // full: a stage known to be whole and inside the matrix (no bounds test
+    // is compiled in); otherwise decided here
+    auto load = [&](auto full, int k0) {
+        constexpr bool FULL = decltype(full)::value;
         // vector loads need the element pair inside one folded block
-        const bool fullA = (m0 + BM <= Mt) && (k0 + KT <= ke) && (!TA || g.M >= 2);
-        const bool fullB = (n0 + BN <= Nt) && (k0 + KT <= ke) && (TB || g.N >= 2);
+        const bool fullA = FULL || ((m0 + BM <= Mt) && (k0 + KT <= ke) && (!TA || g.M >= 2));
+        const bool fullB = FULL || ((n0 + BN <= Nt) && (k0 + KT <= ke) && (TB || g.N >= 2));
 #pragma unroll
         for (int i = 0; i < LA; ++i) {
             const int f = tid + i * NT;
-            if (f >= FA) break;
+            if (FA % NT != 0 && f >= FA) break;
             if (!TA) {
                 const int m = f / (KT / 2), k = 2 * (f % (KT / 2));
                 if (fullA) ra[i] = *reinterpret_cast<const float4*>(A + adA(m0 + m, k0 + k));
@@ -274,7 +305,7 @@ k_cgemm(GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < LB; ++i) {
             const int f = tid + i * NT;
-            if (f >= FB) break;
+            if (FB % NT != 0 && f >= FB) break;
             if (!TB) {
                 const int k = f / (BN / 2), n = 2 * (f % (BN / 2));
                 if (fullB) rb[i] = *reinterpret_cast<const float4*>(B + adB(k0 + k, n0 + n));
@@ -332,7 +363,7 @@ k_cgemm(GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < LA; ++i) {
             const int f = tid + i * NT;
-            if (f >= FA) break;
+            if (FA % NT != 0 && f >= FA) break;
             int m, k, m2, k2;   // element 0 at (m,k), element 1 at (m2,k2)
             if (!TA) { m = f / (KT / 2); k = 2 * (f % (KT / 2)); m2 = m; k2 = k + 1; }
             else { k = f / (BM / 2); m = 2 * (f % (BM / 2)); m2 = m + 1; k2 = k; }
@@ -357,7 +388,7 @@ k_cgemm(GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < LB; ++i) {
             const int f = tid + i * NT;
-            if (f >= FB) break;
+            if (FB % NT != 0 && f >= FB) break;
             int k, n, k2, n2;
             if (!TB) { k = f / (BN / 2); n = 2 * (f % (BN / 2)); k2 = k; n2 = n + 1; }
             else { n = f / (KT / 2); k = 2 * (f % (KT / 2)); n2 = n; k2 = k + 1; }
@@ -468,17 +499,33 @@ k_cgemm(GemmArgs g) {
         }
     };
 
+    // Stages 0 .. nfull-1 of a tile inside the matrix are whole: their loads
+    // are compiled with no bounds test.  Every pass ends with the store of
+    // the stage it loaded.  Both keep the three or four global loads of a
+    // stage issuing back to back: where a bounds-tested load and its
+    // unchecked form write the same registers on merging paths, or a load
+    // may still be outstanding where the loop begins again, the compiler
+    // waits for each load before issuing the next.
+    const bool inner = (m0 + BM <= Mt) && (n0 + BN <= Nt) && (!TA || g.M >= 2) && (TB || g.N >= 2);
     const int nk = (kper + KT - 1) / KT;
-    load(kb);
+    const int nfull = inner ? kper / KT : 0;
+    load(std::false_type{}, kb);
     store(0);
     __syncthreads();
-    for (int t = 0; t < nk; ++t) {
-        const int buf = t & 1;
-        if (t + 1 < nk) load(kb + (t + 1) * KT);
-        compute(buf);
-        if (t + 1 < nk) store(buf ^ 1);
+    int t = 0;
+    for (; t + 1 < nfull; ++t) {
+        load(std::true_type{}, kb + (t + 1) * KT);
+        compute(t & 1);
+        store((t & 1) ^ 1);
         __syncthreads();
     }
+    for (; t + 1 < nk; ++t) {
+        load(std::false_type{}, kb + (t + 1) * KT);
+        compute(t & 1);
+        store((t & 1) ^ 1);
+        __syncthreads();
+    }
+    if (nk > 0) compute((nk - 1) & 1);
 
     // epilogue: acc[i][j][r] is real row 8*(r/4) + 4*half + r%4, column l32
     const bool part = g.splits > 1;
@@ -537,24 +584,25 @@ k_cgemm(GemmArgs g) {
 //   P1 = Ar Br,  P2 = Ai Bi,  P3 = (Ar + Ai)(Br + Bi),
 //   Re C = P1 - P2,  Im C = P3 - P1 - P2,
 // each a real 32 x 32 x 2 MFMA (6 MNK executed flops against 8 MNK for 4M).
-// Operands are staged as three real planes per matrix ([plane][k][m] and
-// [plane][k][n], the sums formed on the way into LDS); a wave owns WMF x WNF
-// blocks of 32 x 32 (complex) outputs with three accumulators each.  Same
+// Operands are staged in LDS as complex rows ([k][m] and [k][n], real and
+// imaginary parts interleaved, as they are in memory), the sum operand formed
+// at read time; a wave owns WMF x WNF blocks of 32 x 32 (complex) outputs
+// with three accumulators each.  Same
 // decomposition (slice-block fold, outer copies, split-K ranges) and the
 // same K order as k_cgemm, so a result does not depend on the tile chosen.
 template <int WGM, int WGN, int WMF, int WNF>
 struct Smem3 {
-    // 16 complex k per stage: the real and imaginary planes only (the sum
-    // plane of 3M is formed from them at read time), double buffered, so
-    // two workgroups still fit a CU
+    // 16 complex k per stage, double buffered
     static constexpr int KT = KT_3M;
     static constexpr int BM = WGM * 32 * WMF;
     static constexpr int BN = WGN * 32 * WNF;
-    // +32 floats per k row: lanes of the two halves of a wave read rows k
-    // and k + 1 in disjoint banks
-    static constexpr int PA = BM + 32;
-    static constexpr int PB = BN + 32;
-    static constexpr size_t bytes = 2 * 2 * (size_t)KT * (PA + PB) * 4;
+    // row pitch in floats, 2 BM + 4: the eight even rows that one 64-bit
+    // store instruction writes when k is the contiguous global index start
+    // in eight different groups of 8 banks, so its 32-lane halves hit 64
+    // distinct banks; a row is 16-byte aligned for the 128-bit stores
+    static constexpr int PA = 2 * BM + 4;
+    static constexpr int PB = 2 * BN + 4;
+    static constexpr size_t bytes = 2 * (size_t)KT * (PA + PB) * 4;
 };
 
 template <int WGM, int WGN, int WMF, int WNF, bool TA, bool TB>
@@ -576,7 +624,7 @@ k_cgemm3m(GemmArgs g) {
     const int tiles_m = (Mt + BM - 1) / BM;
     const int tiles_n = (Nt + BN - 1) / BN;
     const size_t tiles = (size_t)tiles_m * tiles_n;
-    size_t blk = blockIdx.x;
+    size_t blk = xcd_logical(blockIdx.x, gridDim.x);
     const size_t tile = blk % tiles;
     blk /= tiles;
     const int split = (int)(blk % g.splits);
@@ -587,8 +635,8 @@ k_cgemm3m(GemmArgs g) {
     const size_t rr = g.fold == 0 ? blk / g.nb : 0;
     const size_t outer = g.fold == 0 ? rr * g.nb + bb : bb;
     const size_t n_outer = g.fold == 0 ? (size_t)g.nr * g.nb : (size_t)g.nb;
-    const int tm = (int)(tile % tiles_m);
-    const int tn = (int)(tile / tiles_m);
+    int tm, tn;
+    tile_rc(tile, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
     const int kper = g.K / g.splits;
     const int kb = split * kper, ke = kb + kper;
@@ -632,13 +680,14 @@ k_cgemm3m(GemmArgs g) {
         if (n0 + n >= Nt || k >= ke) return make_float2(0.f, 0.f);
         return B[adB(k, n0 + n)];
     };
-    auto load = [&](int k0) {
-        const bool fullA = (m0 + BM <= Mt) && (k0 + KT <= ke) && (!TA || g.M >= 2);
-        const bool fullB = (n0 + BN <= Nt) && (k0 + KT <= ke) && (TB || g.N >= 2);
+    auto load = [&](auto full, int k0) {
+        constexpr bool FULL = decltype(full)::value;
+        const bool fullA = FULL || ((m0 + BM <= Mt) && (k0 + KT <= ke) && (!TA || g.M >= 2));
+        const bool fullB = FULL || ((n0 + BN <= Nt) && (k0 + KT <= ke) && (TB || g.N >= 2));
 #pragma unroll
         for (int i = 0; i < LA; ++i) {
             const int f = tid + i * NT;
-            if (f >= FA) break;
+            if (FA % NT != 0 && f >= FA) break;
             if (!TA) {
                 const int m = f / (KT / 2), k = 2 * (f % (KT / 2));
                 if (fullA) ra[i] = *reinterpret_cast<const float4*>(A + adA(m0 + m, k0 + k));
@@ -658,7 +707,7 @@ k_cgemm3m(GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < LB; ++i) {
             const int f = tid + i * NT;
-            if (f >= FB) break;
+            if (FB % NT != 0 && f >= FB) break;
             if (!TB) {
                 const int k = f / (BN / 2), n = 2 * (f % (BN / 2));
                 if (fullB) rb[i] = *reinterpret_cast<const float4*>(B + adB(k0 + k, n0 + n));
@@ -677,82 +726,68 @@ k_cgemm3m(GemmArgs g) {
         }
     };
 
-    float* As = reinterpret_cast<float*>(smem);     // [2][2][KT][PA]: re, im planes
-    float* Bs = As + 2 * 2 * KT * PA;               // [2][2][KT][PB]
-    constexpr int QA = KT * PA, QB = KT * PB;       // plane strides
-    // Row k of a plane holds column x at x ^ sw(k), sw(k) = 16 ((k/2) mod 4)
-    // (mod the tile width): the four even rows that one store instruction
-    // writes when k is the contiguous global index (A untransposed, B
-    // transposed) then fall in four different bank groups instead of one,
-    // while a half-wave's 32 aligned columns stay 32 distinct banks
-    auto swa = [](int k) { return (((k >> 1) & 3) << 4) & (BM - 1); };
-    auto swb = [](int k) { return (((k >> 1) & 3) << 4) & (BN - 1); };
+    float* As = reinterpret_cast<float*>(smem);     // [2][KT][PA]: complex rows of A
+    float* Bs = As + 2 * KT * PA;                   // [2][KT][PB]: complex rows of B
 
+    // the staged registers go to LDS as they were loaded: one 128-bit store
+    // when the pair is adjacent in a row, two 64-bit stores (rows k, k + 1)
+    // when it runs along k
     auto store = [&](int buf) {
-        float* a = As + buf * 2 * QA;
-        float* b = Bs + buf * 2 * QB;
+        float* a = As + buf * KT * PA;
+        float* b = Bs + buf * KT * PB;
 #pragma unroll
         for (int i = 0; i < LA; ++i) {
             const int f = tid + i * NT;
-            if (f >= FA) break;
+            if (FA % NT != 0 && f >= FA) break;
             const float4 v = ra[i];
             if (TA) {
-                // (m, k), (m + 1, k): adjacent in both planes
-                const int k = f / (BM / 2), m = 2 * (f % (BM / 2)) ^ swa(k);
-                *reinterpret_cast<float2*>(a + k * PA + m) = make_float2(v.x, v.z);
-                *reinterpret_cast<float2*>(a + QA + k * PA + m) = make_float2(v.y, v.w);
+                const int k = f / (BM / 2), m = 2 * (f % (BM / 2));
+                *reinterpret_cast<float4*>(a + k * PA + 2 * m) = v;
             } else {
                 const int m = f / (KT / 2), k = 2 * (f % (KT / 2));
-                const int m0s = m ^ swa(k), m1s = m ^ swa(k + 1);
-                a[k * PA + m0s] = v.x;
-                a[QA + k * PA + m0s] = v.y;
-                a[(k + 1) * PA + m1s] = v.z;
-                a[QA + (k + 1) * PA + m1s] = v.w;
+                *reinterpret_cast<float2*>(a + k * PA + 2 * m) = make_float2(v.x, v.y);
+                *reinterpret_cast<float2*>(a + (k + 1) * PA + 2 * m) = make_float2(v.z, v.w);
             }
         }
 #pragma unroll
         for (int i = 0; i < LB; ++i) {
             const int f = tid + i * NT;
-            if (f >= FB) break;
+            if (FB % NT != 0 && f >= FB) break;
             const float4 v = rb[i];
             if (!TB) {
-                const int k = f / (BN / 2), n = 2 * (f % (BN / 2)) ^ swb(k);
-                *reinterpret_cast<float2*>(b + k * PB + n) = make_float2(v.x, v.z);
-                *reinterpret_cast<float2*>(b + QB + k * PB + n) = make_float2(v.y, v.w);
+                const int k = f / (BN / 2), n = 2 * (f % (BN / 2));
+                *reinterpret_cast<float4*>(b + k * PB + 2 * n) = v;
             } else {
                 const int n = f / (KT / 2), k = 2 * (f % (KT / 2));
-                const int n0s = n ^ swb(k), n1s = n ^ swb(k + 1);
-                b[k * PB + n0s] = v.x;
-                b[QB + k * PB + n0s] = v.y;
-                b[(k + 1) * PB + n1s] = v.z;
-                b[QB + (k + 1) * PB + n1s] = v.w;
+                *reinterpret_cast<float2*>(b + k * PB + 2 * n) = make_float2(v.x, v.y);
+                *reinterpret_cast<float2*>(b + (k + 1) * PB + 2 * n) = make_float2(v.z, v.w);
             }
         }
     };
 
     auto compute = [&](int buf) {
-        const float* a = As + buf * 2 * QA;
-        const float* b = Bs + buf * 2 * QB;
-        // lane (half, l32): A[m = l32][k = half], B[k = half][n = l32];
-        // operands of step ks + 1 are read while the MFMAs of step ks issue;
-        // the third operand of 3M is re + im, formed here in FP32 (the same
-        // rounding as when it was staged as a plane)
+        const float* a = As + buf * KT * PA;
+        const float* b = Bs + buf * KT * PB;
+        // lane (half, l32): A[m = l32][k = half], B[k = half][n = l32], one
+        // 64-bit read each; operands of step ks + 1 are read while the MFMAs
+        // of step ks issue; the third operand of 3M is re + im, formed here
+        // in FP32
         float av[2][WMF][3], bv[2][WNF][3];
         auto rd = [&](int ks, int q) {
             const int kr = 2 * ks + half;
 #pragma unroll
             for (int i = 0; i < WMF; ++i) {
-                const int c = kr * PA + ((wm + i * 32 + l32) ^ swa(kr));
-                av[q][i][0] = a[c];
-                av[q][i][1] = a[QA + c];
-                av[q][i][2] = av[q][i][0] + av[q][i][1];
+                const float2 x = *reinterpret_cast<const float2*>(a + kr * PA + 2 * (wm + i * 32 + l32));
+                av[q][i][0] = x.x;
+                av[q][i][1] = x.y;
+                av[q][i][2] = x.x + x.y;
             }
 #pragma unroll
             for (int j = 0; j < WNF; ++j) {
-                const int c = kr * PB + ((wn + j * 32 + l32) ^ swb(kr));
-                bv[q][j][0] = b[c];
-                bv[q][j][1] = b[QB + c];
-                bv[q][j][2] = bv[q][j][0] + bv[q][j][1];
+                const float2 x = *reinterpret_cast<const float2*>(b + kr * PB + 2 * (wn + j * 32 + l32));
+                bv[q][j][0] = x.x;
+                bv[q][j][1] = x.y;
+                bv[q][j][2] = x.x + x.y;
             }
         };
         rd(0, 0);
@@ -771,17 +806,33 @@ k_cgemm3m(GemmArgs g) {
         }
     };
 
+    // Stages 0 .. nfull-1 of a tile inside the matrix are whole: their loads
+    // are compiled with no bounds test.  Every pass ends with the store of
+    // the stage it loaded.  Both keep the three or four global loads of a
+    // stage issuing back to back: where a bounds-tested load and its
+    // unchecked form write the same registers on merging paths, or a load
+    // may still be outstanding where the loop begins again, the compiler
+    // waits for each load before issuing the next.
+    const bool inner = (m0 + BM <= Mt) && (n0 + BN <= Nt) && (!TA || g.M >= 2) && (TB || g.N >= 2);
     const int nk = (kper + KT - 1) / KT;
-    load(kb);
+    const int nfull = inner ? kper / KT : 0;
+    load(std::false_type{}, kb);
     store(0);
     __syncthreads();
-    for (int t = 0; t < nk; ++t) {
-        const int buf = t & 1;
-        if (t + 1 < nk) load(kb + (t + 1) * KT);
-        compute(buf);
-        if (t + 1 < nk) store(buf ^ 1);
+    int t = 0;
+    for (; t + 1 < nfull; ++t) {
+        load(std::true_type{}, kb + (t + 1) * KT);
+        compute(t & 1);
+        store((t & 1) ^ 1);
         __syncthreads();
     }
+    for (; t + 1 < nk; ++t) {
+        load(std::false_type{}, kb + (t + 1) * KT);
+        compute(t & 1);
+        store((t & 1) ^ 1);
+        __syncthreads();
+    }
+    if (nk > 0) compute((nk - 1) & 1);
 
     // epilogue: acc[i][j][p][r] is row 8*(r/4) + 4*half + r%4, column l32
     const bool part = g.splits > 1;
