@@ -1387,11 +1387,21 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
         if (c.kind == GEMM_MFMA_128x128 && precision == 1) bn = 64;
         if (c.kind == GEMM_MFMA_64x64) { bm = 64; bn = 64; }
         if (c.kind == GEMM_MFMA_128x16) { bm = 128; bn = precision == 1 ? 32 : 16; }
+        // 3M skinny products with at most 64 (32) folded rows and 32 columns:
+        // a 64 x 32 (32 x 32) tile on two waves (one) instead of a 128 x 32
+        // tile that is half (three quarters) zero rows; same MFMA sequence
+        // per output element, so the choice from the folded sizes changes
+        // no result
+        const bool thin3 = precision == 1 && c.kind == GEMM_MFMA_128x16 && Nt <= 32 && Mt <= 64;
+        if (thin3) bm = Mt <= 32 ? 32 : 64;
         const size_t grid = (size_t)((Mt + bm - 1) / bm) * ((Nt + bn - 1) / bn) * batches;
         if (precision == 1) {
-            // 3M tiles: 128 x 128, 64 x 64, and 128 x 32 for the skinny shapes
+            // 3M tiles: 128 x 128, 64 x 64, and 128 x 32 (64 x 32, 32 x 32)
+            // for the skinny shapes
             if (c.kind == GEMM_MFMA_128x128) launch_cfg3<4, 2, 1, 1>(g, grid, s);
             else if (c.kind == GEMM_MFMA_64x64) launch_cfg3<2, 2, 1, 1>(g, grid, s);
+            else if (thin3 && bm == 32) launch_cfg3<1, 1, 1, 1>(g, grid, s);
+            else if (thin3) launch_cfg3<2, 1, 1, 1>(g, grid, s);
             else launch_cfg3<4, 1, 1, 1>(g, grid, s);
         } else if (c.kind == GEMM_MFMA_128x128) launch_prec<4, 2, 1, 4>(g, precision, grid, s);
         else if (c.kind == GEMM_MFMA_64x64) launch_prec<2, 2, 1, 2>(g, precision, grid, s);
