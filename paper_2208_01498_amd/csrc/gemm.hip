@@ -1301,7 +1301,15 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
         else if (g.fold == 2) { g.mA = all; g.mB = 0; }
         g.fold = 0;
     }
-    if (c.swap) {
+    // FP32 3M forms each complex product from three real products, each the
+    // same value whichever operand takes the row role, summed over k in the
+    // same order, so operand roles change no 3M result.  A thin 3M product
+    // (at most 32 folded rows, at least 128 columns) therefore keeps its
+    // roles and takes a 32 x 128 tile: lanes then run along C's contiguous
+    // columns, where the swapped form would write C one 8-byte element per
+    // lane at a stride of the whole row count.
+    const bool wide3 = precision == 1 && c.kind == GEMM_MFMA_128x16 && c.swap && Mt0 <= 32 && Nt0 >= 128;
+    if (c.swap && !wide3) {
         // C^T = B^T A^T, written transposed
         g.A = g0.B; g.B = g0.A;
         g.M = g0.N; g.N = g0.M;
@@ -1394,12 +1402,14 @@ hipError_t launch_gemm(const GemmArgs& g0, int precision, hipStream_t s) {
         // no result
         const bool thin3 = precision == 1 && c.kind == GEMM_MFMA_128x16 && Nt <= 32 && Mt <= 64;
         if (thin3) bm = Mt <= 32 ? 32 : 64;
+        if (wide3) { bm = 32; bn = 128; }
         const size_t grid = (size_t)((Mt + bm - 1) / bm) * ((Nt + bn - 1) / bn) * batches;
         if (precision == 1) {
             // 3M tiles: 128 x 128, 64 x 64, and 128 x 32 (64 x 32, 32 x 32)
             // for the skinny shapes
             if (c.kind == GEMM_MFMA_128x128) launch_cfg3<4, 2, 1, 1>(g, grid, s);
             else if (c.kind == GEMM_MFMA_64x64) launch_cfg3<2, 2, 1, 1>(g, grid, s);
+            else if (wide3) launch_cfg3<1, 4, 1, 1>(g, grid, s);
             else if (thin3 && bm == 32) launch_cfg3<1, 1, 1, 1>(g, grid, s);
             else if (thin3) launch_cfg3<2, 1, 1, 1>(g, grid, s);
             else launch_cfg3<4, 1, 1, 1>(g, grid, s);
