@@ -157,15 +157,18 @@ struct Smem {
     static constexpr int PA = BM + 2;
     static constexpr int PB = BN + 1;            // in 16-byte units
     // 16-bit halves: rows of KT words (one 4-byte word per complex k, its
-    // two 16-bit reals) at a stride of RW = KT + 1 words (odd: rows whose
-    // indices differ mod 32 start in different banks).  A row m sits at
-    // row (m mod 2) GA + m / 2 and real column r of B at (r mod 4) GB + r / 4,
-    // so the rows one store instruction writes (every second A row when m
-    // is the contiguous index, every fourth B column) are consecutive, and
-    // the 32 consecutive rows a half-wave reads stay 32 apart mod 32
-    static constexpr int RW = KT + 1;
-    static constexpr int GA = BM / 2 + 16;
-    static constexpr int GB = BN / 2 + 8;
+    // two 16-bit reals) at a stride of RW = KT + 4 words, so that a lane
+    // reads its 8 reals of an MFMA step as one 16-byte word.  A row m sits
+    // at row (m mod 2) GA + m / 2 and real column r of B at (r mod 4) GB +
+    // r / 4, so the rows one store instruction writes (every second A row
+    // when m is the contiguous index, every fourth B column) are
+    // consecutive.  Row x starts at bank 12 x mod 64, distinct for x mod 16;
+    // with GA = 8 and GB = 4 (mod 16) the 16 rows that 16 consecutive lanes
+    // read (8 in each of two A groups, 4 in each of four B groups) cover
+    // the 64 banks once, so a 16-byte read has no bank conflict
+    static constexpr int RW = KT + 4;
+    static constexpr int GA = (BM / 2 + 15) / 16 * 16 + 8;
+    static constexpr int GB = (BN / 2 + 15) / 16 * 16 + 4;
     static constexpr int RAh = GA + BM / 2;            // rows per A plane
     static constexpr int RBh = 3 * GB + BN / 2;        // rows per B plane
     static constexpr size_t bytes_fp32 = 2 * (size_t)KT * (PA * 8 + PB * 16);
@@ -453,48 +456,52 @@ k_cgemm(GemmArgs g) {
             const uint32_t* bh = Bh + buf * RBh * RW;
             const uint32_t* bl = Bl + buf * RBh * RW;
             // the 8 reals k = 8 half .. 8 half + 7 of a 16-k MFMA step are the
-            // four words 4 half .. 4 half + 3 of the row: four 4-byte reads
-            // at constant offsets from one lane address
+            // four words 4 half .. 4 half + 3 of the row: one 16-byte read
             auto rd8 = [&](const uint32_t* row) {
-                uint32_t v[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = row[q];
-                return __builtin_bit_cast(bf16x8, v);
+                return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(row));
             };
 #pragma unroll
             for (int kc = 0; kc < KT / 8; ++kc) {
-                bf16x8 xh[WMF], xl[WMF], yh[WNF], yl[WNF];
+                // A halves of the step first, then B column block by block:
+                // block j + 1 is read while the MFMAs of block j issue (two
+                // B blocks live instead of WNF keeps the kernel within 128
+                // VGPRs)
+                bf16x8 xh[WMF], xl[WMF], yh[2], yl[2];
 #pragma unroll
                 for (int i = 0; i < WMF; ++i) {
                     const int o = wa(wm + i * 32 + l32, 8 * kc + 4 * half);
                     xh[i] = rd8(ah + o);
                     xl[i] = rd8(al + o);
                 }
+                auto rdb = [&](int j, int q) {
+                    const int o = wb(2 * (wn + j * 16) + l32, 8 * kc + 4 * half);
+                    yh[q] = rd8(bh + o);
+                    yl[q] = rd8(bl + o);
+                };
+                rdb(0, 0);
 #pragma unroll
                 for (int j = 0; j < WNF; ++j) {
-                    const int o = wb(2 * (wn + j * 16) + l32, 8 * kc + 4 * half);
-                    yh[j] = rd8(bh + o);
-                    yl[j] = rd8(bl + o);
-                }
+                    if (j + 1 < WNF) rdb(j + 1, (j + 1) & 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int q = j & 1;
 #pragma unroll
-                for (int i = 0; i < WMF; ++i)
-#pragma unroll
-                    for (int j = 0; j < WNF; ++j) {
+                    for (int i = 0; i < WMF; ++i) {
                         if constexpr (PREC == 3) {
                             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                                __builtin_bit_cast(halfx8, xl[i]), __builtin_bit_cast(halfx8, yh[j]), acc[i][j], 0, 0, 0);
+                                __builtin_bit_cast(halfx8, xl[i]), __builtin_bit_cast(halfx8, yh[q]), acc[i][j], 0, 0, 0);
                             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                                __builtin_bit_cast(halfx8, xh[i]), __builtin_bit_cast(halfx8, yl[j]), acc[i][j], 0, 0, 0);
+                                __builtin_bit_cast(halfx8, xh[i]), __builtin_bit_cast(halfx8, yl[q]), acc[i][j], 0, 0, 0);
                             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                                __builtin_bit_cast(halfx8, xh[i]), __builtin_bit_cast(halfx8, yh[j]), acc[i][j], 0, 0, 0);
+                                __builtin_bit_cast(halfx8, xh[i]), __builtin_bit_cast(halfx8, yh[q]), acc[i][j], 0, 0, 0);
                         } else {
                             if constexpr (PREC == 2) {
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], yh[j], acc[i][j], 0, 0, 0);
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yl[j], acc[i][j], 0, 0, 0);
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], yh[q], acc[i][j], 0, 0, 0);
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yl[q], acc[i][j], 0, 0, 0);
                             }
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yh[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yh[q], acc[i][j], 0, 0, 0);
                         }
                     }
+                }
             }
         }
     };
@@ -515,6 +522,7 @@ k_cgemm(GemmArgs g) {
     int t = 0;
     for (; t + 1 < nfull; ++t) {
         load(std::true_type{}, kb + (t + 1) * KT);
+        __builtin_amdgcn_sched_barrier(0);     // the stage's loads issue before its MFMAs
         compute(t & 1);
         store((t & 1) ^ 1);
         __syncthreads();
