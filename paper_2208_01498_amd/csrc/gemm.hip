@@ -59,7 +59,7 @@ constexpr int KT_FP32 = 8;     // complex k per LDS stage, FP32 (keeps two workg
 constexpr int KT_3M = 16;      // complex k per LDS stage, FP32 3M (two real planes per operand)
 constexpr int KT = 16;         // K granularity of the split-K ranges
 
-constexpr int TILE_GROUP = 8;  // tile rows per group in the tile order (tile_rc)
+constexpr int TILE_GROUP = 4;  // tile rows per group in the tile order (tile_rc)
 
 // Logical index of workgroup b of n: workgroups go to the eight XCDs in
 // turn (b mod 8), each XCD with an L2 of its own; renumbered so that each
