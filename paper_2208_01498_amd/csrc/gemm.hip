@@ -1203,8 +1203,11 @@ GemmChoice choose_gemm(int M, int N, int K, int nbatch, int Mt, int Nt) {
         else if (m >= 64 && n >= 64) tiles = (long long)(m / 64) * (n / 64);
         else tiles = (long long)((m + 127) / 128) * ((n + 15) / 16);
         long long wgs = tiles * nbatch;
+        // an output of at most 32 x 32 per batch entry runs on one-wave
+        // tiles (FP32 3M), which need more K ranges to fill the chip
+        const int cap = (long long)M * N <= 1024 ? 256 : 64;
         int s = 1;
-        while (wgs * s < 512 && (long long)K / (2 * s) >= 4 * KT && s < 64) s *= 2;
+        while (wgs * s < 512 && (long long)K / (2 * s) >= 4 * KT && s < cap) s *= 2;
         c.splits = s;
     }
     // operand roles from the unfolded shape too: computing C^T = B^T A^T sums
