@@ -37,10 +37,10 @@ EXEC = {"fp32": 1.0, "fp32_3m": 0.75, "bf16x3": 3.0, "fp16x3": 3.0, "bf16x1": 1.
 # changed kernel or plan reports null until it is measured again.
 TRAFFIC = [
     {"class": "cgemm_mfma_128x128", "precision": "fp32_3m", "source": "gemm.hip",
-     "source_sha256": "454f270190f7462c6d074de3ad66a756550324904832de31b5f3c34f16e8ce3f",
+     "source_sha256": "a2d73b6a7fe485b7e2eb77a3007b4a9c96b1706633db6faded8abc6ff2fae01e",
      "chunk": 30, "flops_per_amplitude": 40093516002040.0,
-     "bytes_per_launch": 1.618e11,
-     "note": "HBM fetch 1.519e11 + write 9.890e9 bytes per launch (the 153 launches of one "
+     "bytes_per_launch": 1.633e11,
+     "note": "HBM fetch 1.534e11 + write 9.890e9 bytes per launch (the 153 launches of one "
              "timed step; FETCH_SIZE x2.0 and WRITE_SIZE x1.0 from a 1 GiB copy); algorithmic "
              "1.678e10"},
 ]
