@@ -189,9 +189,11 @@ typedef struct tn_exec_stats {
     double algorithmic_flops;         /* sum over executed steps     */
     double permute_bytes;             /* 16 bytes per permuted element */
     /* per kernel class (0 dot-product GEMM for tiny outputs, 1 MFMA GEMM
-     * 64x64 tile, 2 MFMA GEMM 128x128 tile, 3 MFMA GEMM 128x16 tile, 4
-     * permute, 5 leaf gather, 6 MFMA GEMM one wave per 32x32 block for
-     * products of at most 4096 outputs per batch entry): launches, summed
+     * 64x64 tile, 2 MFMA GEMM 128x128 tile (128x64 for FP32 3M), 3 MFMA GEMM
+     * for skinny products (a 128x16 tile; FP32 3M: 128x32, or 64x32, 32x32 and
+     * 32x128 for at most 64 or 32 rows), 4 permute, 5 leaf gather, 6 MFMA GEMM
+     * one wave per 32x32 block for products of at most 4096 outputs per batch
+     * entry): launches, summed
      * device time from HIP events
      * recorded around each launch on the executing stream (only when
      * profiling is on), algorithmic flops (GEMM: 8 per complex multiply-add)
